@@ -1,0 +1,299 @@
+"""Residual A(U), Jacobian G(U), lumped mass and constraints (oracle, test infrastructure only).
+
+Follows the quasi-monolithic semi-linear form (Sec. 2.3, eq. semilinear) with
+no stress split (E_s^+ = E_s, sigma^- = 0), the time-lagged extrapolation
+phi~ in the displacement equation, and its discrete Jacobian
+G_ij = A'(U)(Phi_i, Phi_j) (Sec. 2.4).  Everything is computed by per-cell
+Gauss quadrature into dense element arrays and assembled into SciPy CSR.
+
+Readings of the paper used here (also listed in the design notes):
+* the factor 1/2 in front of d_phi g_kappa(phi) E_s in the phase-field
+  equation is taken literally (ES_FACTOR = 1/2), so that term is
+  (1-kappa) phi E_s(e(u));
+* g_kappa and phi^2 in the displacement equation use phi~ (the extrapolation),
+  which makes the u/phi block of the Jacobian zero (Sec. 3.3);
+* 2D is plane strain: lambda = E nu / ((1+nu)(1-2nu)) in every dimension
+  (the multiple-fracture parameter table lists mu = 4166.6, lambda = 2777.7
+  for E = 1e4, nu = 0.2).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from .fe import Level, gauss_lobatto_01, local_multi_indices
+
+ES_FACTOR = 0.5
+
+
+@dataclass
+class Material:
+    E: float
+    nu: float
+    G_c: float
+    eps: float
+    kappa: float
+    pressure: float
+
+    @property
+    def mu(self) -> float:
+        """Lame mu = E / (2(1+nu))."""
+        return self.E / (2.0 * (1.0 + self.nu))
+
+    @property
+    def lam(self) -> float:
+        """Lame lambda = E nu / ((1+nu)(1-2nu)) (3D and plane strain)."""
+        return self.E * self.nu / ((1.0 + self.nu) * (1.0 - 2.0 * self.nu))
+
+    def g(self, s):
+        """Degradation g_kappa(s) = (1-kappa) s^2 + kappa (Sec. 2.1)."""
+        return (1.0 - self.kappa) * s * s + self.kappa
+
+    def dg(self, s):
+        return 2.0 * (1.0 - self.kappa) * s
+
+    def d2g(self, s):
+        return 2.0 * (1.0 - self.kappa) + 0.0 * s
+
+
+# --------------------------------------------------------------------------
+# Reference tables in physical scale for a level (affine box cells)
+# --------------------------------------------------------------------------
+class CellTables:
+    def __init__(self, lev: Level):
+        d, ref = lev.d, lev.ref
+        self.d = d
+        self.nl = len(ref.nodes)
+        self.N = ref.N                                      # (nq, nl)
+        self.dN = ref.dN_ref / np.array(lev.h)[None, None, :]  # (nq, nl, d)
+        self.JxW = ref.w * lev.jxw_scale                    # (nq,)
+        nq, nl = self.N.shape
+        # displacement test/trial functions Phi_(i,a) = N_a e_i, local index k = i*nl + a
+        grad = np.zeros((nq, d * nl, d, d))
+        for i in range(d):
+            for a in range(nl):
+                grad[:, i * nl + a, i, :] = self.dN[:, a, :]
+        self.grad_w = grad                                  # grad Phi_k (row i = comp)
+        self.eps_w = 0.5 * (grad + np.swapaxes(grad, 2, 3))  # e(Phi_k)
+        self.div_w = np.trace(grad, axis1=2, axis2=3)       # div Phi_k
+
+
+def gather(lev: Level, vec, comp, cells):
+    """Nodal values of one component on the given cells: (nc, nl)."""
+    return vec[comp * lev.n_nodes + lev.conn[cells]]
+
+
+def qp_state(lev: Level, tab: CellTables, mat: Material, U, phit, cells):
+    """Linearization-point quantities at the Gauss points of the given cells."""
+    d = lev.d
+    ue = np.stack([gather(lev, U, i, cells) for i in range(d)], axis=1)   # (nc,d,nl)
+    phie = gather(lev, U, d, cells)                                        # (nc,nl)
+    ptle = phit[lev.conn[cells]]                                           # (nc,nl)
+    grad_u = np.einsum("qaj,cia->cqij", tab.dN, ue)                        # (nc,nq,d,d)
+    e = 0.5 * (grad_u + np.swapaxes(grad_u, 2, 3))
+    tr = np.trace(e, axis1=2, axis2=3)
+    eye = np.eye(d)
+    sigma = 2.0 * mat.mu * e + mat.lam * tr[..., None, None] * eye
+    Es = 0.5 * mat.lam * tr * tr + mat.mu * np.einsum("cqij,cqij->cq", e, e)
+    phi = np.einsum("qa,ca->cq", tab.N, phie)
+    grad_phi = np.einsum("qaj,ca->cqj", tab.dN, phie)
+    phit_q = np.einsum("qa,ca->cq", tab.N, ptle)
+    return dict(e=e, sigma=sigma, Es=Es, div_u=tr, phi=phi, grad_phi=grad_phi, phit=phit_q)
+
+
+# --------------------------------------------------------------------------
+# Element residual and element Jacobian (local order: comp-major, x-fastest nodes)
+# --------------------------------------------------------------------------
+def element_residual(lev, tab, mat, U, phit, cells):
+    """Element vectors of A(U)(Phi_i) on the given cells: (nc, (d+1) nl).
+
+    u rows:   (g(phi~) sigma(u), e(w)) + (phi~^2 p, div w)
+    phi rows: (1/2 g'(phi) E_s(e(u)) + 2 phi p div u - G_c/eps (1-phi), psi)
+              + G_c eps (grad phi, grad psi)
+    """
+    s = qp_state(lev, tab, mat, U, phit, cells)
+    p = mat.pressure
+    gq = mat.g(s["phit"])
+    ru = np.einsum("q,cq,cqij,qkij->ck", tab.JxW, gq, s["sigma"], tab.eps_w)
+    ru += np.einsum("q,cq,qk->ck", tab.JxW, s["phit"] ** 2 * p, tab.div_w)
+    val = (ES_FACTOR * mat.dg(s["phi"]) * s["Es"] + 2.0 * s["phi"] * p * s["div_u"]
+           - mat.G_c / mat.eps * (1.0 - s["phi"]))
+    rphi = np.einsum("q,cq,qa->ca", tab.JxW, val, tab.N)
+    rphi += mat.G_c * mat.eps * np.einsum("q,cqj,qaj->ca", tab.JxW, s["grad_phi"], tab.dN)
+    return np.concatenate([ru, rphi], axis=1)
+
+
+def element_jacobian(lev, tab, mat, U, phit, cells, couple=True):
+    """Dense element Jacobians A'(U)(Phi_i, Phi_j) on the given cells: (nc, nloc, nloc).
+
+    Blocks (rows = test, cols = trial):
+      uu:     (g(phi~) sigma(du), e(w))
+      u phi:  0   (phi~ is fixed; Sec. 3.3)
+      phi u:  (1/2 g'(phi) sigma(u):e(du) + 2 phi p div du, psi)
+      phi phi:(1/2 g''(phi) E_s(e(u)) dphi + 2 p div u dphi + G_c/eps dphi, psi)
+              + G_c eps (grad dphi, grad psi)
+    couple=False drops the phi-u block (the block-diagonal operator B of the smoother).
+    """
+    d, nl = lev.d, tab.nl
+    s = qp_state(lev, tab, mat, U, phit, cells)
+    p = mat.pressure
+    nc = len(cells)
+    nu_ = d * nl
+    K = np.zeros((nc, nu_ + nl, nu_ + nl))
+    eye = np.eye(d)
+    # sigma of every displacement trial function: (nq, k, d, d)
+    sig_w = 2.0 * mat.mu * tab.eps_w + mat.lam * tab.div_w[..., None, None] * eye
+    gq = mat.g(s["phit"])
+    K[:, :nu_, :nu_] = np.einsum("q,cq,qlij,qkij->ckl", tab.JxW, gq, sig_w, tab.eps_w)
+    if couple:
+        sig_e = np.einsum("cqij,qlij->cql", s["sigma"], tab.eps_w)          # sigma(u):e(du)
+        coef = ES_FACTOR * mat.dg(s["phi"])[..., None] * sig_e \
+            + 2.0 * p * s["phi"][..., None] * tab.div_w[None, :, :]
+        K[:, nu_:, :nu_] = np.einsum("q,cql,qa->cal", tab.JxW, coef, tab.N)
+    cphi = ES_FACTOR * mat.d2g(s["phi"]) * s["Es"] + 2.0 * p * s["div_u"] + mat.G_c / mat.eps
+    K[:, nu_:, nu_:] = np.einsum("q,cq,qb,qa->cab", tab.JxW, cphi, tab.N, tab.N)
+    K[:, nu_:, nu_:] += mat.G_c * mat.eps * np.einsum("q,qbj,qaj->ab", tab.JxW, tab.dN, tab.dN)[None]
+    return K
+
+
+def local_dofs(lev: Level, cells):
+    """Global DoF indices of the element arrays, comp-major: (nc, (d+1) nl)."""
+    return np.concatenate([comp * lev.n_nodes + lev.conn[cells] for comp in range(lev.d + 1)], axis=1)
+
+
+# --------------------------------------------------------------------------
+# Assembly
+# --------------------------------------------------------------------------
+def _chunks(n, size):
+    for s in range(0, n, size):
+        yield np.arange(s, min(n, s + size))
+
+
+def chunk_size(lev):
+    nloc = (lev.d + 1) * len(lev.ref.nodes)
+    return max(64, int(2.0e7 // (nloc * nloc)))
+
+
+def assemble_residual(lev, mat, U, phit):
+    """A(U) as a global vector (the Newton residual is R = -A(U))."""
+    tab = CellTables(lev)
+    A = np.zeros(lev.n_dofs)
+    for cells in _chunks(lev.n_cells, chunk_size(lev)):
+        np.add.at(A, local_dofs(lev, cells), element_residual(lev, tab, mat, U, phit, cells))
+    return A
+
+
+def assemble_jacobian(lev, mat, U, phit, couple=True):
+    """Assembled CSR Jacobian G(U) (no constraints)."""
+    tab = CellTables(lev)
+    rows, cols, vals = [], [], []
+    for cells in _chunks(lev.n_cells, chunk_size(lev)):
+        K = element_jacobian(lev, tab, mat, U, phit, cells, couple)
+        ld = local_dofs(lev, cells)
+        rows.append(np.repeat(ld, ld.shape[1], axis=1).ravel())
+        cols.append(np.tile(ld, (1, ld.shape[1])).ravel())
+        vals.append(K.ravel())
+    G = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(lev.n_dofs, lev.n_dofs)).tocsr()
+    G.sum_duplicates()
+    return G
+
+
+def apply_ebe(lev, mat, U, phit, x, couple=True):
+    """Element-by-element apply y = G(U) x (no assembly), for sizes where CSR is too big."""
+    tab = CellTables(lev)
+    y = np.zeros(lev.n_dofs)
+    for cells in _chunks(lev.n_cells, chunk_size(lev)):
+        K = element_jacobian(lev, tab, mat, U, phit, cells, couple)
+        ld = local_dofs(lev, cells)
+        np.add.at(y, ld, np.einsum("ckl,cl->ck", K, x[ld]))
+    return y
+
+
+def cells_touching_nodes(lev, nodes):
+    """Indices of active cells that contain any of the given nodes."""
+    hit = np.zeros(lev.n_nodes, dtype=bool)
+    hit[np.asarray(nodes)] = True
+    return np.nonzero(hit[lev.conn].any(axis=1))[0]
+
+
+def jacobian_rows(lev, mat, U, phit, x, rows, couple=True):
+    """Selected entries (G(U) x)[rows], from the element arrays of the cells around them."""
+    rows = np.asarray(rows)
+    nodes = rows % lev.n_nodes
+    cells = cells_touching_nodes(lev, nodes)
+    tab = CellTables(lev)
+    y = np.zeros(lev.n_dofs)
+    for sl in _chunks(len(cells), chunk_size(lev)):
+        c = cells[sl]
+        K = element_jacobian(lev, tab, mat, U, phit, c, couple)
+        ld = local_dofs(lev, c)
+        np.add.at(y, ld, np.einsum("ckl,cl->ck", K, x[ld]))
+    return y[rows]
+
+
+def residual_rows(lev, mat, U, phit, rows):
+    rows = np.asarray(rows)
+    cells = cells_touching_nodes(lev, rows % lev.n_nodes)
+    tab = CellTables(lev)
+    A = np.zeros(lev.n_dofs)
+    np.add.at(A, local_dofs(lev, cells), element_residual(lev, tab, mat, U, phit, cells))
+    return A[rows]
+
+
+# --------------------------------------------------------------------------
+# Lumped mass (Sec. 3.1, remark on M: Gauss-Lobatto quadrature -> diagonal)
+# --------------------------------------------------------------------------
+def lumped_mass(lev: Level):
+    """Diagonal M_ii = sum over cells of the Gauss-Lobatto weight of node i times |cell|.
+
+    The Gauss-Lobatto points of Q_p are its nodes, so N_j(x_i) = delta_ij and the
+    quadrature mass matrix is diagonal.  Pinned: sum_i M_ii = |domain|.
+    """
+    _, w1 = gauss_lobatto_01(lev.p)
+    M = np.zeros(lev.n_nodes)
+    for ia, a in enumerate(local_multi_indices(lev.d, lev.p + 1)):
+        wa = np.prod([w1[ak] for ak in a]) * lev.jxw_scale
+        np.add.at(M, lev.conn[:, ia], wa)
+    return M
+
+
+# --------------------------------------------------------------------------
+# Constraints (Sec. 3.1 Algorithm 1 step 4; Sec. 4 constraint matrix C)
+# --------------------------------------------------------------------------
+def constrained_dofs(lev: Level, dirichlet_faces: int, active_phi=None, extra_u_bits=None):
+    """Boolean per-DoF constraint flag.
+
+    Displacement DoFs: Dirichlet faces, extra per-node component bits
+    (bit i = u_i), hole nodes.  Phase-field DoFs: active set, hole nodes.
+    """
+    d, nn = lev.d, lev.n_nodes
+    c = np.zeros(lev.n_dofs, dtype=bool)
+    bnd = lev.boundary_face_nodes(dirichlet_faces)
+    for i in range(d):
+        ci = bnd | lev.hole_node
+        if extra_u_bits is not None:
+            ci = ci | ((np.asarray(extra_u_bits) >> i) & 1).astype(bool)
+        c[i * nn:(i + 1) * nn] = ci
+    cphi = lev.hole_node.copy()
+    if active_phi is not None:
+        cphi |= np.asarray(active_phi).astype(bool)
+    c[d * nn:] = cphi
+    return c
+
+
+def constrain_matrix(G, constrained):
+    """G~ = Pi_F G Pi_F + Pi_C: eliminate constrained rows and columns, unit diagonal."""
+    free = (~constrained).astype(np.float64)
+    F = sp.diags(free)
+    return (F @ G @ F + sp.diags(constrained.astype(np.float64))).tocsr()
+
+
+def constrain_rhs(G, R, constrained, d_lift):
+    """R~ = Pi_F (R - G d) + d with the lift d supported on the constrained DoFs."""
+    d_lift = np.where(constrained, d_lift, 0.0)
+    out = R - G @ d_lift
+    out[constrained] = d_lift[constrained]
+    return out
