@@ -1,0 +1,234 @@
+/*
+ * pff.h -- C ABI of the matrix-free phase-field fracture Newton/GMG library (gfx950).
+ *
+ * The library implements one step of the primal-dual active-set (semi-smooth
+ * Newton) method for the quasi-monolithic pressurized phase-field fracture
+ * problem of Jodlbauer, Langer and Wick, "Matrix-free multigrid solvers for
+ * phase-field fracture problems" (arXiv:1902.08112):
+ *   - the semi-linear form A(u, phi) (Sec. 2.3, eq. semilinear, no stress
+ *     split, time-lagged extrapolation phi~ in the displacement equation) and
+ *     its Jacobian G = A'(U) on Q1/Q2 quadrilaterals / hexahedra (Sec. 2.4);
+ *   - the matrix-free cell-loop apply y = G~ x (Sec. 4.1) with rows and
+ *     columns of the constrained DoFs eliminated (Algorithm 1, step 4);
+ *   - coarse-level operators rediscretized at the injected linearization
+ *     point G_l(U_l) with the injected active set (Sec. 4.2);
+ *   - the monolithic geometric-multigrid V-cycle P_full = MG(G~) with a
+ *     block-diagonal Chebyshev-Jacobi smoother and a Chebyshev coarse solve
+ *     (Sec. 3.2, Sec. 3.3);
+ *   - right-preconditioned FGMRES (Sec. 3, Sec. 5) inside one Newton step.
+ *
+ * Conventions shared by every call
+ *   Vector layout: component-major blocks [u_1 | ... | u_d | phi]; each block
+ *     covers the level's bounding-box node lattice, nn_k = p*N_k + 1 nodes per
+ *     axis, x fastest, then y, then z.  A level vector has (d+1)*prod(nn_k)
+ *     entries.  Lattice nodes of no active cell (the hole of the L-shaped
+ *     domain) are stored, constrained in every component, and held at 0.
+ *   Levels: l = 0 is the coarsest, l = n_levels-1 the finest; N_l = N_fine / 2^(L-1-l).
+ *   Pointers marked d_ are device pointers on the current HIP device; they
+ *     are owned by the caller.  The library never allocates or frees device
+ *     memory: every device buffer it uses is carved from the caller's workspace.
+ *   Streams: `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Calls are stream-ordered; only the calls documented as
+ *     synchronizing wait for the stream.
+ *   Errors: every call returns a pf_status; on failure pf_last_error() gives a
+ *     message.  Arguments are validated before any device work; the library
+ *     never aborts the process.
+ *   Threads: one context per host thread.
+ */
+#ifndef PFF_H
+#define PFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int pf_status;
+#define PF_OK 0
+#define PF_ERR_INVALID_ARG 1
+#define PF_ERR_UNSUPPORTED 2
+#define PF_ERR_DEVICE 3
+#define PF_ERR_WORKSPACE 4
+#define PF_ERR_NOT_CONVERGED 5
+#define PF_ERR_NONFINITE 6
+
+#define PF_F64 0
+#define PF_F32 1
+
+#define PF_BOX 0
+#define PF_LSHAPE 1 /* [0,1]^3 minus [0.5,1]x[0.5,1]x[0,1] (2D: the same without z), scaled by extent */
+
+/* Per-node constraint bits (uint8): bit c < d constrains u_c, bit 3 constrains phi. */
+#define PF_MASK_U(c) (1u << (c))
+#define PF_MASK_PHI 8u
+
+typedef struct pf_mesh {
+  int dim;                  /* 2 or 3 */
+  int degree;               /* 1 (Q1) or 2 (Q2) */
+  int n_cells[3];           /* finest-level cells per axis (unused entries ignored) */
+  double extent[3];         /* box edge lengths */
+  int domain;               /* PF_BOX or PF_LSHAPE */
+  int n_levels;             /* >= 1; n_cells divisible by 2^(n_levels-1) */
+  unsigned dirichlet_faces; /* u = current value on faces: bit 2k = {x_k = 0}, bit 2k+1 = {x_k = extent_k} */
+} pf_mesh;
+
+/* Solver constants.  pf_default_options gives the paper's values:
+ * Chebyshev degree 4 over [1.2 lam/5, 1.2 lam] with lam from 10 CG steps
+ * (Sec. 3.2.1), coarse Chebyshev over [0.9 lam_min, 1.2 lam_max] (Sec. 3.2.2)
+ * with 2 sweeps of degree 20, PDAS constant c = 100 (Sec. 3.1), FGMRES
+ * restart 50 and relative tolerance 1e-8. */
+typedef struct pf_options {
+  int vcycle_precision;    /* PF_F64 or PF_F32 (V-cycle levels above the coarsest) */
+  int cheb_degree;         /* smoother polynomial degree (operator applications per step) */
+  double cheb_ratio;       /* lower end of the smoothing range = upper / ratio */
+  double cheb_safety;      /* upper end = safety * estimated lam_max */
+  int eig_cg_steps;        /* CG steps of the eigenvalue estimate */
+  int coarse_degree;       /* Chebyshev degree of the coarse solve */
+  int coarse_sweeps;       /* outer sweeps of the coarse solve */
+  double coarse_lo_factor; /* coarse range lower end = factor * lam_min */
+  int gmres_restart;       /* FGMRES restart length m (workspace grows with m) */
+  int gmres_max_iter;      /* total FGMRES iteration cap */
+  double gmres_rtol;       /* stop when ||R~ - G~ dU|| <= rtol ||R~|| (true residual) */
+  double pdas_c;           /* active-set constant c */
+  uint64_t eig_seed;       /* SplitMix64 seed of the eigenvalue start vectors */
+} pf_options;
+
+typedef struct pf_newton_report {
+  int gmres_iters;          /* FGMRES iterations of this step */
+  int converged;            /* 1 if the true relative residual reached gmres_rtol */
+  double rel_residual;      /* ||R~ - G~ dU|| / ||R~|| (FP64, recomputed) */
+  double rhs_norm;          /* ||R~|| */
+  int64_t n_active;         /* |A_k|: phase-field nodes in the active set */
+  double t_residual_s;      /* wall time of step 1 (residual) */
+  double t_setup_s;         /* wall time of steps 2-4 (active set, level data, diagonals, eigenvalues) */
+  double t_solve_s;         /* wall time of step 5 (FGMRES) */
+  double t_total_s;
+} pf_newton_report;
+
+typedef struct pf_level_info {
+  int n_cells[3];
+  int n_nodes_axis[3];
+  int64_t n_nodes;
+  int64_t n_dofs;
+  int64_t n_active_cells;
+  double h[3];
+  int precision;            /* arithmetic type of this level inside the V-cycle */
+} pf_level_info;
+
+typedef struct pf_ctx pf_ctx;
+
+/* Fill *opt with the paper's constants (see pf_options). */
+void pf_default_options(pf_options* opt);
+
+/* Device bytes of the workspace pf_setup needs for this mesh and options.
+ * Errors: PF_ERR_INVALID_ARG (null pointer, bad mesh), PF_ERR_UNSUPPORTED (dim, degree). */
+pf_status pf_workspace_size(const pf_mesh* mesh, const pf_options* opt, size_t* bytes);
+
+/* Create a context.  Material (Sec. 2.1): Young's modulus E > 0, Poisson
+ * ratio -1 < nu < 0.5 (mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu)) in 2D
+ * and 3D), critical energy release rate G_c > 0, phase-field width eps > 0,
+ * residual stiffness 0 <= kappa < 1, constant pressure p (finite).  opt may
+ * be NULL (defaults).  d_workspace: device buffer of at least
+ * pf_workspace_size bytes, 256-byte aligned, owned by the caller and kept
+ * alive until pf_destroy.  Builds the level geometry, Dirichlet/hole masks and
+ * the lumped mass (Sec. 3.1 remark, Gauss-Lobatto) on `stream`.
+ * Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE (too small / misaligned), DEVICE. */
+pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double eps, double kappa,
+                   double pressure, const pf_options* opt, void* d_workspace, size_t ws_bytes,
+                   void* stream, pf_ctx** out);
+
+/* Extra prescribed-displacement constraints on the finest level: one byte per
+ * node, bit c constrains u_c (e.g. a loaded strip).  Coarser levels inherit
+ * them by nodal injection.  d_bits may be NULL to clear. */
+pf_status pf_set_constraints(pf_ctx* ctx, const uint8_t* d_bits, void* stream);
+
+/* Set the linearization point on the finest level and build every level's
+ * data: nodal injection of U, phi~ and the active indicator (Sec. 4.2),
+ * constraint masks, matrix-free diagonals (Sec. 4.1 remark), FP32 copies, and
+ * the eigenvalue estimates of every level and block (unless fixed by
+ * pf_set_eig_bounds).  d_U: (d+1)*n_nodes FP64; d_phi_tilde: n_nodes FP64;
+ * d_active: n_nodes bytes (nonzero = phi constrained), may be NULL.
+ * Synchronizes the stream (reads back the Lanczos coefficients). */
+pf_status pf_set_linearization(pf_ctx* ctx, const double* d_U, const double* d_phi_tilde,
+                               const uint8_t* d_active, void* stream);
+
+/* y = G~_l(U_l) x on level l: y = Pi_F G Pi_F x + Pi_C x (Sec. 4.1 eq. for
+ * G u as a sum over cells; Algorithm 1 step 4 elimination).  prec PF_F64:
+ * x, y are double*; PF_F32: float* (uses the FP32 copy of the level data).
+ * Requires pf_set_linearization.  Asynchronous. */
+pf_status pf_jacobian_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream);
+
+/* Block-diagonal smoother operator B~_l x = diag(G_uu, G_phiphi) with the same
+ * elimination (S_full of Sec. 3.3).  Same conventions as pf_jacobian_apply. */
+pf_status pf_block_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream);
+
+/* R = -A(U) on the finest level (Algorithm 1 step 1; Sec. 4.1 remark), no
+ * constraints applied.  d_U: (d+1)*n_nodes, d_phi_tilde: n_nodes, d_R: (d+1)*n_nodes, FP64. */
+pf_status pf_residual(pf_ctx* ctx, const double* d_U, const double* d_phi_tilde, double* d_R, void* stream);
+
+/* Copy the diagonal of G~_l (1 on constrained rows) of level l into d_diag (FP64). */
+pf_status pf_get_diagonal(pf_ctx* ctx, int level, double* d_diag, void* stream);
+
+/* Copy the lumped mass of the finest level (n_nodes FP64) into d_M. */
+pf_status pf_get_lumped_mass(pf_ctx* ctx, double* d_M, void* stream);
+
+/* Copy the level's injected linearization point (d_U: (d+1)*n_nodes, may be NULL),
+ * phi~ (n_nodes, may be NULL) and constraint mask bytes (n_nodes, may be NULL). */
+pf_status pf_get_level_data(pf_ctx* ctx, int level, double* d_U, double* d_phi_tilde, uint8_t* d_mask,
+                            void* stream);
+
+/* Active-set decision (Algorithm 1 step 3): for every phase-field node that
+ * is not otherwise constrained, v = R_phi/M + c (phi - phi^old); active iff
+ * v > 0.  d_R: -A(U) (FP64, full vector), d_U, d_U_old: full vectors.
+ * Writes d_active (n_nodes bytes, 1 = active), optionally d_v (n_nodes FP64,
+ * 0 on skipped nodes), and the count into *n_active (synchronizes if non-NULL). */
+pf_status pf_active_set(pf_ctx* ctx, const double* d_R, const double* d_U, const double* d_U_old,
+                        uint8_t* d_active, double* d_v, int64_t* n_active, void* stream);
+
+/* Transfers between level l (fine) and l-1 (coarse), FP64, whole vectors:
+ * op 0: out_c = P^T in_f (restriction, Sec. 3.2), op 1: out_f = P in_c
+ * (prolongation), op 2: out_c = nodal injection of in_f (Sec. 4.2).  No masks. */
+pf_status pf_transfer(pf_ctx* ctx, int level, int op, const double* d_in, double* d_out, void* stream);
+
+/* Eigenvalue estimates (raw Ritz values, before the safety factors) of
+ * D^{-1} B~_bb per block on level l: out[0..3] = {lam_min_u, lam_max_u,
+ * lam_min_phi, lam_max_phi}.  pf_set_eig_bounds fixes them (they are then
+ * kept by pf_set_linearization until cleared with in == NULL). */
+pf_status pf_get_eig_bounds(pf_ctx* ctx, int level, double out[4]);
+pf_status pf_set_eig_bounds(pf_ctx* ctx, int level, const double in[4]);
+
+/* z = P_full^{-1} r: one V-cycle (Sec. 3.3) with one pre- and one post-
+ * smoothing step, prec = PF_F64 or PF_F32 for the levels above the coarsest
+ * (the coarse solve is FP64).  r, z: fine-level FP64 vectors; z vanishes on
+ * constrained DoFs and the constrained entries of r are ignored.  Asynchronous. */
+pf_status pf_vcycle(pf_ctx* ctx, int prec, const double* d_r, double* d_z, void* stream);
+
+/* One iteration k of Algorithm 1 (Sec. 3.1): residual, active set, level data,
+ * FGMRES with the V-cycle (opt->vcycle_precision), update.  d_U (in/out):
+ * U_k -> U_{k+1}; d_U_old: the previous time step (phi^old); d_phi_tilde:
+ * extrapolated phase field for the displacement equation.  Dirichlet DoFs
+ * keep their current values.  Synchronizes.  Returns PF_ERR_NOT_CONVERGED
+ * (report filled, U updated with the last iterate) if gmres_max_iter is reached,
+ * PF_ERR_NONFINITE if the residual is not finite (U unchanged). */
+pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde,
+                         pf_newton_report* rep, void* stream);
+
+/* Level sizes. */
+pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
+
+/* Change the V-cycle precision used by pf_newton_step (PF_F64 or PF_F32). */
+pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec);
+
+/* Release the context (host memory only; the workspace stays the caller's). */
+void pf_destroy(pf_ctx* ctx);
+
+const char* pf_status_string(pf_status s);
+/* Message of the last failed call on this thread ("" if none). */
+const char* pf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFF_H */

@@ -1,0 +1,193 @@
+// Internal declarations of the pff library (gfx950 HIP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/pff.h"
+
+namespace pff {
+
+// ---------------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define PFF_HIP(...)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (__VA_ARGS__);                                                                  \
+    if (e_ != hipSuccess) {                                                                    \
+      ::pff::set_error(std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));                     \
+      return PF_ERR_DEVICE;                                                                    \
+    }                                                                                          \
+  } while (0)
+
+#define PFF_CHECK_LAUNCH()                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = hipGetLastError();                                                         \
+    if (e_ != hipSuccess) {                                                                    \
+      ::pff::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));                \
+      return PF_ERR_DEVICE;                                                                    \
+    }                                                                                          \
+  } while (0)
+
+#define PFF_TRY(...)                                                                           \
+  do {                                                                                         \
+    pf_status s_ = (__VA_ARGS__);                                                                   \
+    if (s_ != PF_OK) return s_;                                                                \
+  } while (0)
+
+constexpr int kMaskPhi = 8;
+
+__host__ __device__ inline int mask_bit(int comp, int d) { return comp < d ? (1 << comp) : kMaskPhi; }
+
+// ---------------------------------------------------------------------------
+// level geometry and cell-operator parameters
+// ---------------------------------------------------------------------------
+struct Geom {
+  int d, p;
+  int N[3];        // cells per axis (1 for unused axes)
+  int nn[3];       // nodes per axis (1 for unused axes)
+  int64_t ns[3];   // node strides (x fastest)
+  int64_t n_nodes, n_dofs, n_cells;
+  double h[3];
+  double ext[3];
+  int lshape;
+};
+
+// Parameters of every cell-loop kernel (passed by value).
+struct CellParams {
+  int N[3];
+  int nn[3];
+  int64_t ns[3];
+  int64_t n_nodes;
+  int64_t n_cells;
+  int lshape;
+  double inv_h[3];
+  double vol;          // cell volume (JxW = w_q * vol)
+  double mu, lam, kappa, pres, gc_over_eps, gc_eps;
+};
+
+// Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p.
+struct Material {
+  double mu, lam, Gc, eps, kappa, p;
+};
+
+CellParams make_cell_params(const Geom& g, const Material& m);
+
+__host__ __device__ inline bool cell_in_hole(int lshape, int cx, int cy, int Nx, int Ny) {
+  return lshape && (2 * cx >= Nx) && (2 * cy >= Ny);
+}
+
+// Cell-loop modes.
+enum CellMode {
+  MODE_APPLY = 0,  // y += Pi_F G Pi_F x   (y pre-set to Pi_C x)
+  MODE_BLOCK = 1,  // same with the phi-u coupling removed (smoother operator B)
+  MODE_RAW = 2,    // y += G x, no constraints
+  MODE_RESID = 3,  // y += -A(U)
+  MODE_DIAG = 4,   // y += diag(G) (constrained rows set to 1 afterwards)
+};
+
+// Launch the cell loop on level data.  T = double or float.  For MODE_RESID
+// and MODE_DIAG x is ignored.  y is accumulated into (callers pre-set it).
+template <typename T>
+pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                      const uint8_t* mask, T* y, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// vector kernels (vec.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+pf_status vec_fill(T* y, T v, int64_t n, hipStream_t s);
+template <typename T>
+pf_status vec_copy(T* y, const T* x, int64_t n, hipStream_t s);
+template <typename Tin, typename Tout>
+pf_status vec_cast(Tout* y, const Tin* x, int64_t n, hipStream_t s);
+// y_i = constrained ? x_i : 0   (x may be null -> 0)
+template <typename T>
+pf_status vec_init_constrained(T* y, const T* x, const uint8_t* mask, int64_t nn, int d, hipStream_t s);
+// y_i = constrained ? v : y_i
+template <typename T>
+pf_status vec_set_constrained(T* y, T v, const uint8_t* mask, int64_t nn, int d, hipStream_t s);
+// y = a*x + b*y
+template <typename T>
+pf_status vec_axpby(T* y, T a, const T* x, T b, int64_t n, hipStream_t s);
+// z = x - y
+template <typename T>
+pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s);
+// Chebyshev step (per block coefficients c1[2], c2[2]; blocks u / phi):
+//   first:  d = c2 * Dinv * res;           x += d
+//   other:  res -= t; d = c1*d + c2*Dinv*res; x += d
+template <typename T>
+pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
+                        int first, int64_t nn, int d, hipStream_t s);
+// dots per block: out[0] = sum over u-block of x*y, out[1] over the phi-block (FP64 accumulation)
+pf_status dot_blocks(const double* x, const double* y, int64_t nn, int d, double* d_partials, double* h_out,
+                     hipStream_t s);
+// ||x||^2 (FP64) into host
+pf_status dot_host(const double* x, const double* y, int64_t n, double* d_partials, double* h_out, hipStream_t s);
+// h_dev[i] = V_i . w for i < k (V rows of length n, stride ld); FP64
+pf_status multi_dot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* d_partials,
+                    double* d_h, hipStream_t s);
+// w -= sum_i h[i] V_i   (h on device)
+pf_status multi_axpy(double* w, const double* V, int64_t ld, int k, const double* d_h, int64_t n, double sign,
+                     hipStream_t s);
+// y = x * (1/sqrt(*d_nrm2))
+pf_status vec_scale_inv_sqrt(double* y, const double* x, const double* d_nrm2, int64_t n, hipStream_t s);
+// sum of squares into d_out (device scalar)
+pf_status nrm2_dev(const double* x, int64_t n, double* d_partials, double* d_out, hipStream_t s);
+// count of non-finite entries (host)
+pf_status count_nonfinite(const double* x, int64_t n, double* d_partials, double* h_out, hipStream_t s);
+// SplitMix64 start vector of the eigenvalue estimate (block-local counters), masked
+pf_status eig_start_vector(double* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_phi,
+                           hipStream_t s);
+// y_i = x_i * dinv_i where dinv = 1/diag (constrained rows: 0)
+pf_status vec_jacobi(double* y, const double* x, const double* diag, const uint8_t* mask, int64_t nn, int d,
+                     hipStream_t s);
+// per block: y_b = x_b + beta_b * y_b / y_b -= alpha_b * x_b
+pf_status vec_xpby_blocks(double* y, const double* x, const double beta[2], int64_t nn, int d, hipStream_t s);
+pf_status vec_axpy_blocks(double* y, const double* x, const double alpha[2], int64_t nn, int d, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// structured grid kernels (grid.hip)
+// ---------------------------------------------------------------------------
+// masks: Dirichlet faces and hole
+pf_status build_base_mask(const Geom& g, unsigned faces, uint8_t* mask, hipStream_t s);
+// coarse[j] = fine[inj(j)] for ncomp components (fine -> coarse nodal injection)
+template <typename T>
+pf_status inject(const Geom& gc, const Geom& gf, const T* fine, T* coarse, int ncomp, hipStream_t s);
+// coarse_mask[j] = fine_mask[inj(j)] | base[j]
+pf_status inject_mask(const Geom& gc, const Geom& gf, const uint8_t* fine, const uint8_t* base, uint8_t* coarse,
+                      hipStream_t s);
+// restriction out_c = [mask_c] P^T in_f ; in_f read as is
+template <typename Tin, typename Tout>
+pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, Tout* out_c, const uint8_t* mask_c,
+                       hipStream_t s);
+// prolongation: out_f = (add ? out_f : 0) + [mask_f] P in_c
+template <typename Tin, typename Tout>
+pf_status prolong_vec(const Geom& gc, const Geom& gf, const Tin* in_c, Tout* out_f, const uint8_t* mask_f, int add,
+                      hipStream_t s);
+// lumped mass on the node lattice
+pf_status lumped_mass(const Geom& g, double* M, hipStream_t s);
+// active set decision; active bytes, v values, and mask |= 8 for active nodes
+pf_status pdas_decide(const Geom& g, const double* R, const double* U, const double* Uold, const double* M,
+                      const uint8_t* base_mask, double c, uint8_t* active, double* v, hipStream_t s);
+// count of nonzero bytes (host result)
+pf_status count_bytes(const uint8_t* a, int64_t n, double* d_partials, int64_t* h_out, hipStream_t s);
+// mask = base | extra | (active ? 8 : 0)
+pf_status combine_mask(const uint8_t* base, const uint8_t* extra, const uint8_t* active, uint8_t* mask, int64_t n,
+                       hipStream_t s);
+// lift d = Pi_C,phi-active (Uold - U) (only phi block on active nodes), else 0
+pf_status build_lift(const Geom& g, const double* U, const double* Uold, const uint8_t* active, double* dl,
+                     hipStream_t s);
+// Rt_i = constrained ? dl_i : R_i - t_i
+pf_status constrain_rhs(const Geom& g, const double* R, const double* t, const double* dl, const uint8_t* mask,
+                        double* Rt, hipStream_t s);
+
+constexpr int kRedBlock = 256;
+constexpr int kRedMaxBlocks = 1024;
+
+}  // namespace pff

@@ -1,0 +1,1073 @@
+// Host orchestration and the C ABI: context and workspace carve-up, level data
+// (Sec. 4.2), eigenvalue estimates (Sec. 3.2.1), the V-cycle (Sec. 3.2, 3.3),
+// FGMRES with CGS2 (Sec. 3, 5) and one active-set Newton step (Algorithm 1).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace pff {
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+pf_status launch_cell_generic_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
+                                const uint8_t*, double*, hipStream_t);
+pf_status launch_cell_generic_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
+                                const uint8_t*, float*, hipStream_t);
+pf_status launch_cell_q1_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
+                           const uint8_t*, double*, hipStream_t, bool* handled);
+pf_status launch_cell_q1_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
+                           const uint8_t*, float*, hipStream_t, bool* handled);
+
+template <>
+pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
+                              const double* phit, const uint8_t* mask, double* y, hipStream_t s) {
+  bool handled = false;
+  pf_status st = launch_cell_q1_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
+  if (handled) return st;
+  return launch_cell_generic_d(g, cp, mode, x, U, phit, mask, y, s);
+}
+template <>
+pf_status launch_cell<float>(const Geom& g, const CellParams& cp, int mode, const float* x, const float* U,
+                             const float* phit, const uint8_t* mask, float* y, hipStream_t s) {
+  bool handled = false;
+  pf_status st = launch_cell_q1_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
+  if (handled) return st;
+  return launch_cell_generic_f(g, cp, mode, x, U, phit, mask, y, s);
+}
+
+// modes whose output starts from Pi_C x (identity rows on constrained DoFs)
+static bool starts_from_constrained(int mode) { return mode == MODE_APPLY || mode == MODE_BLOCK; }
+
+// overwrite y with the operator result on one level's data
+template <typename T>
+pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                   const uint8_t* mask, T* y, hipStream_t s) {
+  if (starts_from_constrained(mode)) {
+    PFF_TRY(vec_init_constrained<T>(y, x, mask, g.n_nodes, g.d, s));
+  } else {
+    PFF_TRY(vec_fill<T>(y, T(0), g.n_dofs, s));
+  }
+  PFF_TRY(launch_cell<T>(g, cp, mode, x, U, phit, mask, y, s));
+  if (mode == MODE_DIAG) PFF_TRY(vec_set_constrained<T>(y, T(1), mask, g.n_nodes, g.d, s));
+  return PF_OK;
+}
+
+// y = constrained ? 0 : x  (with type conversion)
+template <typename Tin, typename Tout>
+__global__ void k_mask_free(Tout* y, const Tin* x, const uint8_t* mask, int64_t nn, int d) {
+  const int64_t n = (int64_t)(d + 1) * nn;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i / nn);
+    const int64_t node = i - (int64_t)c * nn;
+    y[i] = (mask[node] & mask_bit(c, d)) ? Tout(0) : (Tout)x[i];
+  }
+}
+template <typename Tin, typename Tout>
+pf_status mask_free(Tout* y, const Tin* x, const uint8_t* mask, int64_t nn, int d, hipStream_t s) {
+  int64_t n = (int64_t)(d + 1) * nn;
+  int64_t nb = std::min<int64_t>(65536, std::max<int64_t>(1, (n + 255) / 256));
+  k_mask_free<Tin, Tout><<<nb, 256, 0, s>>>(y, x, mask, nn, d);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+// eigenvalues of a symmetric tridiagonal matrix by Sturm-sequence bisection
+static int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double bb = i ? b[i - 1] * b[i - 1] : 0.0;
+    q = a[i] - x - (i ? bb / q : 0.0);
+    if (q == 0.0) q = 1e-300;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+static double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int k) {
+  // k-th smallest eigenvalue (0-based)
+  double lo = 1e300, hi = -1e300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(a, b, mid) > k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace pff
+
+using namespace pff;
+
+struct LevelBuf {
+  Geom g;
+  double *U = nullptr, *phit = nullptr, *diag = nullptr;
+  float *U32 = nullptr, *phit32 = nullptr, *diag32 = nullptr;
+  uint8_t *base = nullptr, *mask = nullptr;
+  void *vb = nullptr, *vx = nullptr, *vr = nullptr, *vt = nullptr, *vd = nullptr;
+  double eig[4] = {1, 1, 1, 1};
+  bool eig_fixed = false;
+  int64_t n_active_cells = 0;
+};
+
+struct pf_ctx {
+  pf_mesh mesh;
+  Material mat;
+  pf_options opt;
+  std::vector<LevelBuf> lev;
+  double *M = nullptr, *R = nullptr, *dl = nullptr, *Rt = nullptr, *dU = nullptr, *t = nullptr;
+  uint8_t *extra = nullptr, *active = nullptr;
+  double *V = nullptr, *Z = nullptr;
+  double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
+  bool has_extra = false, has_lin = false;
+  size_t ws_bytes = 0;
+  int vprec = PF_F64;
+};
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T) + 256;
+    return p;
+  }
+};
+
+pf_status validate_mesh(const pf_mesh* m) {
+  if (!m) {
+    set_error("mesh is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (m->dim != 2 && m->dim != 3) {
+    set_error("dim must be 2 or 3");
+    return PF_ERR_UNSUPPORTED;
+  }
+  if (m->degree != 1 && m->degree != 2) {
+    set_error("degree must be 1 or 2");
+    return PF_ERR_UNSUPPORTED;
+  }
+  if (m->n_levels < 1 || m->n_levels > 16) {
+    set_error("n_levels must be in [1, 16]");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (m->domain != PF_BOX && m->domain != PF_LSHAPE) {
+    set_error("domain must be PF_BOX or PF_LSHAPE");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int s = 1 << (m->n_levels - 1);
+  for (int k = 0; k < m->dim; ++k) {
+    if (m->n_cells[k] < 1 || m->n_cells[k] % s != 0) {
+      set_error("n_cells must be positive and divisible by 2^(n_levels-1)");
+      return PF_ERR_INVALID_ARG;
+    }
+    if (!(m->extent[k] > 0.0) || !std::isfinite(m->extent[k])) {
+      set_error("extent must be positive and finite");
+      return PF_ERR_INVALID_ARG;
+    }
+    if ((int64_t)m->n_cells[k] * m->degree + 1 > (1 << 24)) {
+      set_error("too many nodes per axis");
+      return PF_ERR_INVALID_ARG;
+    }
+  }
+  if (m->domain == PF_LSHAPE) {
+    for (int k = 0; k < 2; ++k)
+      if ((m->n_cells[k] / s) % 2 != 0) {
+        set_error("L-shape needs an even number of coarsest-level cells in x and y");
+        return PF_ERR_INVALID_ARG;
+      }
+  }
+  if (m->dirichlet_faces >> (2 * m->dim)) {
+    set_error("dirichlet_faces has bits beyond 2*dim");
+    return PF_ERR_INVALID_ARG;
+  }
+  return PF_OK;
+}
+
+pf_status validate_opts(const pf_options* o) {
+  if (o->vcycle_precision != PF_F64 && o->vcycle_precision != PF_F32) {
+    set_error("vcycle_precision must be PF_F64 or PF_F32");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (o->cheb_degree < 1 || o->cheb_degree > 64 || o->coarse_degree < 1 || o->coarse_degree > 256 ||
+      o->coarse_sweeps < 1 || o->coarse_sweeps > 64) {
+    set_error("Chebyshev degrees / sweeps out of range");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!(o->cheb_ratio > 1.0) || !(o->cheb_safety > 0.0) || !(o->coarse_lo_factor > 0.0)) {
+    set_error("Chebyshev range factors out of range");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (o->eig_cg_steps < 1 || o->eig_cg_steps > 100) {
+    set_error("eig_cg_steps must be in [1, 100]");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (o->gmres_restart < 1 || o->gmres_restart > 200 || o->gmres_max_iter < 1 || !(o->gmres_rtol > 0.0)) {
+    set_error("FGMRES settings out of range (restart in [1, 200])");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!std::isfinite(o->pdas_c) || !(o->pdas_c >= 0.0)) {
+    set_error("pdas_c must be finite and >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  return PF_OK;
+}
+
+Geom level_geom(const pf_mesh& m, int l) {
+  Geom g;
+  std::memset(&g, 0, sizeof(g));
+  g.d = m.dim;
+  g.p = m.degree;
+  const int sh = m.n_levels - 1 - l;
+  int64_t stride = 1;
+  g.n_cells = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (k < m.dim) {
+      g.N[k] = m.n_cells[k] >> sh;
+      g.nn[k] = m.degree * g.N[k] + 1;
+      g.h[k] = m.extent[k] / g.N[k];
+      g.ext[k] = m.extent[k];
+    } else {
+      g.N[k] = 1;
+      g.nn[k] = 1;
+      g.h[k] = 1.0;
+      g.ext[k] = 1.0;
+    }
+    g.ns[k] = stride;
+    stride *= g.nn[k];
+    g.n_cells *= g.N[k];
+  }
+  g.n_nodes = stride;
+  g.n_dofs = (int64_t)(m.dim + 1) * stride;
+  g.lshape = m.domain == PF_LSHAPE;
+  return g;
+}
+
+// Carve every device buffer; with base == nullptr only the size is computed.
+size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
+  Carver cv{base};
+  const int L = m.n_levels;
+  std::vector<LevelBuf> lev(L);
+  for (int l = 0; l < L; ++l) {
+    LevelBuf& b = lev[l];
+    b.g = level_geom(m, l);
+    const size_t nn = b.g.n_nodes, nd = b.g.n_dofs;
+    b.U = cv.take<double>(nd);
+    b.phit = cv.take<double>(nn);
+    b.diag = cv.take<double>(nd);
+    b.U32 = cv.take<float>(nd);
+    b.phit32 = cv.take<float>(nn);
+    b.diag32 = cv.take<float>(nd);
+    b.base = cv.take<uint8_t>(nn);
+    b.mask = cv.take<uint8_t>(nn);
+    b.vb = cv.take<double>(nd);
+    b.vx = cv.take<double>(nd);
+    b.vr = cv.take<double>(nd);
+    b.vt = cv.take<double>(nd);
+    b.vd = cv.take<double>(nd);
+  }
+  const Geom& gf = lev[L - 1].g;
+  const size_t nn = gf.n_nodes, nd = gf.n_dofs;
+  const int mr = o.gmres_restart;
+  double* M = cv.take<double>(nn);
+  double* R = cv.take<double>(nd);
+  double* dl = cv.take<double>(nd);
+  double* Rt = cv.take<double>(nd);
+  double* dU = cv.take<double>(nd);
+  double* t = cv.take<double>(nd);
+  uint8_t* extra = cv.take<uint8_t>(nn);
+  uint8_t* active = cv.take<uint8_t>(nn);
+  double* V = cv.take<double>((size_t)(mr + 1) * nd);
+  double* Z = cv.take<double>((size_t)mr * nd);
+  double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
+  double* part_md = cv.take<double>((size_t)256 * (mr + 2));
+  double* dscal = cv.take<double>(1024);
+  if (c) {
+    c->lev = lev;
+    c->M = M;
+    c->R = R;
+    c->dl = dl;
+    c->Rt = Rt;
+    c->dU = dU;
+    c->t = t;
+    c->extra = extra;
+    c->active = active;
+    c->V = V;
+    c->Z = Z;
+    c->part = part;
+    c->part_md = part_md;
+    c->dscal = dscal;
+  }
+  return cv.off + 256;
+}
+
+CellParams cparams(pf_ctx* c, int l) { return make_cell_params(c->lev[l].g, c->mat); }
+
+int level_prec(pf_ctx* c, int l, int vprec) { return l == 0 ? PF_F64 : vprec; }
+
+// ---------------------------------------------------------------------------
+// operator on level l in precision prec (x, y point to that precision)
+// ---------------------------------------------------------------------------
+pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  const CellParams cp = cparams(c, l);
+  if (prec == PF_F64)
+    return apply_op<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s);
+  return apply_op<float>(b.g, cp, mode, (const float*)x, b.U32, b.phit32, b.mask, (float*)y, s);
+}
+
+// Chebyshev coefficients of step k for one block: interval [lo, hi]
+struct ChebCoef {
+  std::vector<double> c1, c2;
+};
+ChebCoef cheb_coefs(double lo, double hi, int degree) {
+  ChebCoef r;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  r.c1.push_back(0.0);
+  r.c2.push_back(1.0 / theta);
+  for (int k = 1; k < degree; ++k) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    r.c1.push_back(rn * rho);
+    r.c2.push_back(2.0 * rn / delta);
+    rho = rn;
+  }
+  return r;
+}
+
+// x += Cheb_B(res) with per-block intervals; res is overwritten; uses vd, vt of the level
+template <typename T>
+pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2], const double hi[2], int degree,
+                   hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  const ChebCoef cu = cheb_coefs(lo[0], hi[0], degree), cpz = cheb_coefs(lo[1], hi[1], degree);
+  T* dv = (T*)b.vd;
+  T* t = (T*)b.vt;
+  const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
+  for (int k = 0; k < degree; ++k) {
+    if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s));
+    const double c1[2] = {cu.c1[k], cpz.c1[k]}, c2[2] = {cu.c2[k], cpz.c2[k]};
+    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? 1 : 0, b.g.n_nodes, b.g.d, s));
+  }
+  return PF_OK;
+}
+
+// one smoothing step x += Cheb_B(b - G~ x)
+template <typename T>
+pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  T* bb = (T*)b.vb;
+  T* x = (T*)b.vx;
+  T* r = (T*)b.vr;
+  if (x_zero) {
+    PFF_TRY(vec_copy<T>(r, bb, b.g.n_dofs, s));
+  } else {
+    PFF_TRY(level_apply(c, l, prec, MODE_APPLY, x, b.vt, s));
+    PFF_TRY(vec_sub<T>(r, bb, (T*)b.vt, b.g.n_dofs, s));
+  }
+  const pf_options& o = c->opt;
+  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
+  const double lo[2] = {hi[0] / o.cheb_ratio, hi[1] / o.cheb_ratio};
+  return cheb_run<T>(c, l, prec, r, x, lo, hi, o.cheb_degree, s);
+}
+
+pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
+  LevelBuf& b = c->lev[0];
+  double* bb = (double*)b.vb;
+  double* x = (double*)b.vx;
+  double* r = (double*)b.vr;
+  const pf_options& o = c->opt;
+  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
+  const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
+  PFF_TRY(vec_fill<double>(x, 0.0, b.g.n_dofs, s));
+  for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
+    if (sw == 0) {
+      PFF_TRY(vec_copy<double>(r, bb, b.g.n_dofs, s));
+    } else {
+      PFF_TRY(level_apply(c, 0, PF_F64, MODE_APPLY, x, b.vt, s));
+      PFF_TRY(vec_sub<double>(r, bb, (double*)b.vt, b.g.n_dofs, s));
+    }
+    PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, s));
+  }
+  return PF_OK;
+}
+
+template <typename Tf, typename Tc>
+pf_status restrict_to(pf_ctx* c, int l, hipStream_t s) {
+  LevelBuf& f = c->lev[l];
+  LevelBuf& co = c->lev[l - 1];
+  return restrict_vec<Tf, Tc>(co.g, f.g, (const Tf*)f.vr, (Tc*)co.vb, co.mask, s);
+}
+template <typename Tc, typename Tf>
+pf_status prolong_add(pf_ctx* c, int l, hipStream_t s) {
+  LevelBuf& f = c->lev[l];
+  LevelBuf& co = c->lev[l - 1];
+  return prolong_vec<Tc, Tf>(co.g, f.g, (const Tc*)co.vx, (Tf*)f.vx, f.mask, 1, s);
+}
+
+pf_status vcycle_level(pf_ctx* c, int l, int vprec, hipStream_t s) {
+  if (l == 0) return coarse_solve(c, s);
+  const int pl = level_prec(c, l, vprec), pc = level_prec(c, l - 1, vprec);
+  LevelBuf& b = c->lev[l];
+  if (pl == PF_F64) {
+    PFF_TRY(vec_fill<double>((double*)b.vx, 0.0, b.g.n_dofs, s));
+    PFF_TRY(smooth<double>(c, l, pl, true, s));
+    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s));
+    PFF_TRY(vec_sub<double>((double*)b.vr, (double*)b.vb, (double*)b.vt, b.g.n_dofs, s));
+    PFF_TRY(pc == PF_F64 ? restrict_to<double, double>(c, l, s) : restrict_to<double, float>(c, l, s));
+  } else {
+    PFF_TRY(vec_fill<float>((float*)b.vx, 0.0f, b.g.n_dofs, s));
+    PFF_TRY(smooth<float>(c, l, pl, true, s));
+    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s));
+    PFF_TRY(vec_sub<float>((float*)b.vr, (float*)b.vb, (float*)b.vt, b.g.n_dofs, s));
+    PFF_TRY(pc == PF_F64 ? restrict_to<float, double>(c, l, s) : restrict_to<float, float>(c, l, s));
+  }
+  PFF_TRY(vcycle_level(c, l - 1, vprec, s));
+  if (pl == PF_F64) {
+    PFF_TRY(pc == PF_F64 ? prolong_add<double, double>(c, l, s) : prolong_add<float, double>(c, l, s));
+    PFF_TRY(smooth<double>(c, l, pl, false, s));
+  } else {
+    PFF_TRY(pc == PF_F64 ? prolong_add<double, float>(c, l, s) : prolong_add<float, float>(c, l, s));
+    PFF_TRY(smooth<float>(c, l, pl, false, s));
+  }
+  return PF_OK;
+}
+
+pf_status vcycle(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
+  const int L = (int)c->lev.size() - 1;
+  LevelBuf& f = c->lev[L];
+  const int pl = level_prec(c, L, vprec);
+  if (pl == PF_F64)
+    PFF_TRY(mask_free<double, double>((double*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s));
+  else
+    PFF_TRY(mask_free<double, float>((float*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s));
+  PFF_TRY(vcycle_level(c, L, vprec, s));
+  if (pl == PF_F64)
+    PFF_TRY(mask_free<double, double>(z, (const double*)f.vx, f.mask, f.g.n_nodes, f.g.d, s));
+  else
+    PFF_TRY(mask_free<float, double>(z, (const float*)f.vx, f.mask, f.g.n_nodes, f.g.d, s));
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// eigenvalue estimates: PCG on D^{-1} B~_bb per block (both blocks in one apply)
+// ---------------------------------------------------------------------------
+pf_status estimate_eigs(pf_ctx* c, int l, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  const Geom& g = b.g;
+  double* r = (double*)b.vr;
+  double* z = (double*)b.vd;
+  double* p = (double*)b.vb;
+  double* Ap = (double*)b.vt;
+  const uint64_t seed = c->opt.eig_seed;
+  const uint64_t su = seed + (uint64_t)l * 0x1000003ull + 0ull * 0x10001ull;
+  const uint64_t sp = seed + (uint64_t)l * 0x1000003ull + 1ull * 0x10001ull;
+  PFF_TRY(eig_start_vector(r, b.mask, g.n_nodes, g.d, su, sp, s));
+  PFF_TRY(vec_jacobi(z, r, b.diag, b.mask, g.n_nodes, g.d, s));
+  PFF_TRY(vec_copy<double>(p, z, g.n_dofs, s));
+  double rz[2], rz0[2], pAp[2], rzn[2];
+  PFF_TRY(dot_blocks(r, z, g.n_nodes, g.d, c->part, rz, s));
+  rz0[0] = rz[0];
+  rz0[1] = rz[1];
+  bool done[2] = {!(rz0[0] > 0), !(rz0[1] > 0)};
+  std::vector<double> al[2], be[2];
+  const CellParams cp = cparams(c, l);
+  for (int it = 0; it < c->opt.eig_cg_steps; ++it) {
+    for (int k = 0; k < 2; ++k)
+      if (!done[k] && (rz[k] <= 0.0 || rz[k] <= 1e-24 * rz0[k])) done[k] = true;
+    if (done[0] && done[1]) break;
+    PFF_TRY(apply_op<double>(g, cp, MODE_BLOCK, p, b.U, b.phit, b.mask, Ap, s));
+    PFF_TRY(dot_blocks(p, Ap, g.n_nodes, g.d, c->part, pAp, s));
+    double alpha[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+      if (done[k]) continue;
+      if (!(pAp[k] > 0.0)) {
+        done[k] = true;
+        continue;
+      }
+      alpha[k] = rz[k] / pAp[k];
+      al[k].push_back(alpha[k]);
+    }
+    const double nal[2] = {-alpha[0], -alpha[1]};
+    PFF_TRY(vec_axpy_blocks(r, Ap, nal, g.n_nodes, g.d, s));
+    PFF_TRY(vec_jacobi(z, r, b.diag, b.mask, g.n_nodes, g.d, s));
+    PFF_TRY(dot_blocks(r, z, g.n_nodes, g.d, c->part, rzn, s));
+    double beta[2] = {0, 0};
+    for (int k = 0; k < 2; ++k) {
+      if (done[k]) continue;
+      beta[k] = rzn[k] / rz[k];
+      be[k].push_back(beta[k]);
+      rz[k] = rzn[k];
+    }
+    PFF_TRY(vec_xpby_blocks(p, z, beta, g.n_nodes, g.d, s));
+  }
+  for (int k = 0; k < 2; ++k) {
+    const size_t n = al[k].size();
+    if (n == 0) {
+      b.eig[2 * k] = 1.0;
+      b.eig[2 * k + 1] = 1.0;
+      continue;
+    }
+    std::vector<double> a(n), off(n > 1 ? n - 1 : 0);
+    for (size_t j = 0; j < n; ++j) {
+      a[j] = 1.0 / al[k][j] + (j ? be[k][j - 1] / al[k][j - 1] : 0.0);
+      if (j + 1 < n) off[j] = std::sqrt(be[k][j]) / al[k][j];
+    }
+    b.eig[2 * k] = tridiag_eig(a, off, 0);
+    b.eig[2 * k + 1] = tridiag_eig(a, off, (int)n - 1);
+  }
+  return PF_OK;
+}
+
+pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, const uint8_t* active, hipStream_t s) {
+  const int L = (int)c->lev.size() - 1;
+  LevelBuf& f = c->lev[L];
+  PFF_TRY(vec_copy<double>(f.U, U, f.g.n_dofs, s));
+  PFF_TRY(vec_copy<double>(f.phit, phit, f.g.n_nodes, s));
+  PFF_TRY(combine_mask(f.base, c->has_extra ? c->extra : nullptr, active, f.mask, f.g.n_nodes, s));
+  for (int l = L - 1; l >= 0; --l) {
+    LevelBuf& co = c->lev[l];
+    LevelBuf& fi = c->lev[l + 1];
+    PFF_TRY(inject<double>(co.g, fi.g, fi.U, co.U, co.g.d + 1, s));
+    PFF_TRY(inject<double>(co.g, fi.g, fi.phit, co.phit, 1, s));
+    PFF_TRY(inject_mask(co.g, fi.g, fi.mask, co.base, co.mask, s));
+  }
+  for (int l = 0; l <= L; ++l) {
+    LevelBuf& b = c->lev[l];
+    PFF_TRY(apply_op<double>(b.g, cparams(c, l), MODE_DIAG, nullptr, b.U, b.phit, b.mask, b.diag, s));
+    PFF_TRY(vec_cast<double, float>(b.U32, b.U, b.g.n_dofs, s));
+    PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
+    PFF_TRY(vec_cast<double, float>(b.diag32, b.diag, b.g.n_dofs, s));
+  }
+  for (int l = 0; l <= L; ++l)
+    if (!c->lev[l].eig_fixed) PFF_TRY(estimate_eigs(c, l, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  c->has_lin = true;
+  return PF_OK;
+}
+
+// Givens-based FGMRES(m), right preconditioned by the V-cycle, CGS2 Arnoldi.
+pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, double* rel, double* bnorm_out,
+                 hipStream_t s) {
+  const int L = (int)c->lev.size() - 1;
+  LevelBuf& f = c->lev[L];
+  const int64_t n = f.g.n_dofs;
+  const int m = c->opt.gmres_restart;
+  const CellParams cp = cparams(c, L);
+  double bn2 = 0;
+  PFF_TRY(dot_host(b, b, n, c->part, &bn2, s));
+  const double bnorm = std::sqrt(bn2);
+  *bnorm_out = bnorm;
+  const double tol = c->opt.gmres_rtol * bnorm;
+  auto true_res = [&](double* beta) -> pf_status {
+    PFF_TRY(apply_op<double>(f.g, cp, MODE_APPLY, x, f.U, f.phit, f.mask, c->t, s));
+    PFF_TRY(vec_sub<double>(c->V, b, c->t, n, s));
+    double r2 = 0;
+    PFF_TRY(dot_host(c->V, c->V, n, c->part, &r2, s));
+    *beta = std::sqrt(r2);
+    return PF_OK;
+  };
+  double beta = 0;
+  PFF_TRY(true_res(&beta));
+  int total = 0;
+  std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+  std::vector<double> hbuf(2 * (m + 1) + 2);
+  while (beta > tol && total < c->opt.gmres_max_iter) {
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    // V_0 = r / beta (r already in V_0)
+    double* dnorm = c->dscal + 520;
+    hbuf[0] = beta * beta;
+    PFF_HIP(hipMemcpyAsync(dnorm, hbuf.data(), sizeof(double), hipMemcpyHostToDevice, s));
+    PFF_TRY(vec_scale_inv_sqrt(c->V, c->V, dnorm, n, s));
+    PFF_HIP(hipStreamSynchronize(s));
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = c->V + (int64_t)j * n;
+      double* zj = c->Z + (int64_t)j * n;
+      double* w = c->V + (int64_t)(j + 1) * n;
+      PFF_TRY(vcycle(c, vprec, vj, zj, s));
+      PFF_TRY(apply_op<double>(f.g, cp, MODE_APPLY, zj, f.U, f.phit, f.mask, w, s));
+      double* h1 = c->dscal;
+      double* h2 = c->dscal + 256;
+      double* nr = c->dscal + 512;
+      PFF_TRY(multi_dot(c->V, n, j + 1, w, n, c->part_md, h1, s));
+      PFF_TRY(multi_axpy(w, c->V, n, j + 1, h1, n, -1.0, s));
+      PFF_TRY(multi_dot(c->V, n, j + 1, w, n, c->part_md, h2, s));
+      PFF_TRY(multi_axpy(w, c->V, n, j + 1, h2, n, -1.0, s));
+      PFF_TRY(nrm2_dev(w, n, c->part, nr, s));
+      PFF_TRY(vec_scale_inv_sqrt(w, w, nr, n, s));
+      PFF_HIP(hipMemcpyAsync(hbuf.data(), c->dscal, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+      PFF_HIP(hipMemcpyAsync(hbuf.data() + (m + 1), h2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
+      PFF_HIP(hipMemcpyAsync(hbuf.data() + 2 * (m + 1), nr, sizeof(double), hipMemcpyDeviceToHost, s));
+      PFF_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hbuf[i] + hbuf[(m + 1) + i];
+      H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(0.0, hbuf[2 * (m + 1)]));
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bq;
+      }
+      const double a = H[(size_t)j * m + j], bq = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, bq);
+      if (den == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        cs[j] = a / den;
+        sn[j] = bq / den;
+      }
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      jend = j + 1;
+      if (!std::isfinite(g[j + 1])) {
+        set_error("FGMRES produced a non-finite residual estimate");
+        return PF_ERR_NONFINITE;
+      }
+      if (std::fabs(g[j + 1]) <= tol || total >= c->opt.gmres_max_iter || den == 0.0) break;
+    }
+    // back substitution H y = g
+    for (int i = jend - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k = i + 1; k < jend; ++k) acc -= H[(size_t)i * m + k] * y[k];
+      y[i] = H[(size_t)i * m + i] != 0.0 ? acc / H[(size_t)i * m + i] : 0.0;
+    }
+    double* dy = c->dscal + 640;
+    PFF_HIP(hipMemcpyAsync(dy, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, s));
+    PFF_TRY(multi_axpy(x, c->Z, n, jend, dy, n, 1.0, s));
+    PFF_HIP(hipStreamSynchronize(s));
+    PFF_TRY(true_res(&beta));
+  }
+  *iters = total;
+  *rel = bnorm > 0 ? beta / bnorm : 0.0;
+  return PF_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+hipStream_t st(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+void pf_default_options(pf_options* o) {
+  if (!o) return;
+  o->vcycle_precision = PF_F64;
+  o->cheb_degree = 4;
+  o->cheb_ratio = 5.0;
+  o->cheb_safety = 1.2;
+  o->eig_cg_steps = 10;
+  o->coarse_degree = 20;
+  o->coarse_sweeps = 2;
+  o->coarse_lo_factor = 0.9;
+  o->gmres_restart = 50;
+  o->gmres_max_iter = 500;
+  o->gmres_rtol = 1e-8;
+  o->pdas_c = 100.0;
+  o->eig_seed = 12345;
+}
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "PF_OK";
+    case PF_ERR_INVALID_ARG: return "PF_ERR_INVALID_ARG";
+    case PF_ERR_UNSUPPORTED: return "PF_ERR_UNSUPPORTED";
+    case PF_ERR_DEVICE: return "PF_ERR_DEVICE";
+    case PF_ERR_WORKSPACE: return "PF_ERR_WORKSPACE";
+    case PF_ERR_NOT_CONVERGED: return "PF_ERR_NOT_CONVERGED";
+    case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE";
+    default: return "PF_ERR_UNKNOWN";
+  }
+}
+
+const char* pf_last_error(void) { return g_err.c_str(); }
+
+pf_status pf_workspace_size(const pf_mesh* mesh, const pf_options* opt, size_t* bytes) {
+  if (!bytes) {
+    set_error("bytes is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  PFF_TRY(validate_mesh(mesh));
+  pf_options o;
+  pf_default_options(&o);
+  if (opt) o = *opt;
+  PFF_TRY(validate_opts(&o));
+  *bytes = carve(nullptr, *mesh, o, nullptr);
+  return PF_OK;
+}
+
+pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double eps, double kappa, double pressure,
+                   const pf_options* opt, void* d_workspace, size_t ws_bytes, void* stream, pf_ctx** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  PFF_TRY(validate_mesh(mesh));
+  pf_options o;
+  pf_default_options(&o);
+  if (opt) o = *opt;
+  PFF_TRY(validate_opts(&o));
+  if (!(E > 0.0) || !std::isfinite(E) || !(nu > -1.0 && nu < 0.5) || !(G_c > 0.0) || !std::isfinite(G_c) ||
+      !(eps > 0.0) || !std::isfinite(eps) || !(kappa >= 0.0 && kappa < 1.0) || !std::isfinite(pressure)) {
+    set_error("material parameters out of range (E>0, -1<nu<0.5, G_c>0, eps>0, 0<=kappa<1, finite p)");
+    return PF_ERR_INVALID_ARG;
+  }
+  const size_t need = carve(nullptr, *mesh, o, nullptr);
+  if (!d_workspace || ws_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return PF_ERR_WORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return PF_ERR_WORKSPACE;
+  }
+  pf_ctx* c = new pf_ctx();
+  c->mesh = *mesh;
+  c->opt = o;
+  c->vprec = o.vcycle_precision;
+  c->mat.mu = E / (2.0 * (1.0 + nu));
+  c->mat.lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  c->mat.Gc = G_c;
+  c->mat.eps = eps;
+  c->mat.kappa = kappa;
+  c->mat.p = pressure;
+  c->ws_bytes = ws_bytes;
+  carve(c, *mesh, o, reinterpret_cast<char*>(d_workspace));
+  hipStream_t s = st(stream);
+  const int L = mesh->n_levels;
+  for (int l = 0; l < L; ++l) {
+    LevelBuf& b = c->lev[l];
+    int64_t act = 0;
+    for (int64_t cy = 0; cy < b.g.N[1]; ++cy)
+      for (int64_t cx = 0; cx < b.g.N[0]; ++cx) act += cell_in_hole(b.g.lshape, (int)cx, (int)cy, b.g.N[0], b.g.N[1]) ? 0 : 1;
+    b.n_active_cells = act * b.g.N[2];
+    pf_status r = build_base_mask(b.g, mesh->dirichlet_faces, b.base, s);
+    if (r == PF_OK) r = vec_copy<uint8_t>(b.mask, b.base, b.g.n_nodes, s);
+    if (r != PF_OK) {
+      delete c;
+      return r;
+    }
+  }
+  pf_status r = lumped_mass(c->lev[L - 1].g, c->M, s);
+  if (r != PF_OK) {
+    delete c;
+    return r;
+  }
+  *out = c;
+  return PF_OK;
+}
+
+void pf_destroy(pf_ctx* ctx) { delete ctx; }
+
+#define NEED_CTX()                     \
+  if (!ctx) {                          \
+    set_error("context is NULL");      \
+    return PF_ERR_INVALID_ARG;         \
+  }
+#define NEED_LIN()                                                    \
+  if (!ctx->has_lin) {                                                \
+    set_error("no linearization point: call pf_set_linearization"); \
+    return PF_ERR_INVALID_ARG;                                        \
+  }
+#define NEED_LEVEL(l)                                   \
+  if ((l) < 0 || (l) >= (int)ctx->lev.size()) {         \
+    set_error("level out of range");                    \
+    return PF_ERR_INVALID_ARG;                          \
+  }
+
+pf_status pf_set_constraints(pf_ctx* ctx, const uint8_t* d_bits, void* stream) {
+  NEED_CTX();
+  if (!d_bits) {
+    ctx->has_extra = false;
+    return PF_OK;
+  }
+  LevelBuf& f = ctx->lev.back();
+  PFF_TRY(vec_copy<uint8_t>(ctx->extra, d_bits, f.g.n_nodes, st(stream)));
+  ctx->has_extra = true;
+  return PF_OK;
+}
+
+pf_status pf_set_linearization(pf_ctx* ctx, const double* d_U, const double* d_phi_tilde, const uint8_t* d_active,
+                               void* stream) {
+  NEED_CTX();
+  if (!d_U || !d_phi_tilde) {
+    set_error("U and phi_tilde must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  return set_linearization(ctx, d_U, d_phi_tilde, d_active, st(stream));
+}
+
+static pf_status apply_entry(pf_ctx* ctx, int level, int prec, int mode, const void* d_x, void* d_y, void* stream) {
+  NEED_CTX();
+  NEED_LIN();
+  NEED_LEVEL(level);
+  if (prec != PF_F64 && prec != PF_F32) {
+    set_error("prec must be PF_F64 or PF_F32");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!d_x || !d_y) {
+    set_error("x and y must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (d_x == d_y) {
+    set_error("x and y must not alias");
+    return PF_ERR_INVALID_ARG;
+  }
+  return level_apply(ctx, level, prec, mode, d_x, d_y, st(stream));
+}
+
+pf_status pf_jacobian_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream) {
+  return apply_entry(ctx, level, prec, MODE_APPLY, d_x, d_y, stream);
+}
+
+pf_status pf_block_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream) {
+  return apply_entry(ctx, level, prec, MODE_BLOCK, d_x, d_y, stream);
+}
+
+pf_status pf_residual(pf_ctx* ctx, const double* d_U, const double* d_phi_tilde, double* d_R, void* stream) {
+  NEED_CTX();
+  if (!d_U || !d_phi_tilde || !d_R) {
+    set_error("U, phi_tilde and R must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  LevelBuf& f = ctx->lev.back();
+  return apply_op<double>(f.g, cparams(ctx, (int)ctx->lev.size() - 1), MODE_RESID, nullptr, d_U, d_phi_tilde,
+                          f.mask, d_R, st(stream));
+}
+
+pf_status pf_get_diagonal(pf_ctx* ctx, int level, double* d_diag, void* stream) {
+  NEED_CTX();
+  NEED_LIN();
+  NEED_LEVEL(level);
+  if (!d_diag) {
+    set_error("diag is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  LevelBuf& b = ctx->lev[level];
+  return vec_copy<double>(d_diag, b.diag, b.g.n_dofs, st(stream));
+}
+
+pf_status pf_get_lumped_mass(pf_ctx* ctx, double* d_M, void* stream) {
+  NEED_CTX();
+  if (!d_M) {
+    set_error("M is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  return vec_copy<double>(d_M, ctx->M, ctx->lev.back().g.n_nodes, st(stream));
+}
+
+pf_status pf_get_level_data(pf_ctx* ctx, int level, double* d_U, double* d_phi_tilde, uint8_t* d_mask,
+                            void* stream) {
+  NEED_CTX();
+  NEED_LEVEL(level);
+  LevelBuf& b = ctx->lev[level];
+  hipStream_t s = st(stream);
+  if ((d_U || d_phi_tilde) && !ctx->has_lin) {
+    set_error("no linearization point: call pf_set_linearization");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (d_U) PFF_TRY(vec_copy<double>(d_U, b.U, b.g.n_dofs, s));
+  if (d_phi_tilde) PFF_TRY(vec_copy<double>(d_phi_tilde, b.phit, b.g.n_nodes, s));
+  if (d_mask) PFF_TRY(vec_copy<uint8_t>(d_mask, b.mask, b.g.n_nodes, s));
+  return PF_OK;
+}
+
+pf_status pf_active_set(pf_ctx* ctx, const double* d_R, const double* d_U, const double* d_U_old, uint8_t* d_active,
+                        double* d_v, int64_t* n_active, void* stream) {
+  NEED_CTX();
+  if (!d_R || !d_U || !d_U_old || !d_active) {
+    set_error("R, U, U_old and active must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  LevelBuf& f = ctx->lev.back();
+  hipStream_t s = st(stream);
+  PFF_TRY(pdas_decide(f.g, d_R, d_U, d_U_old, ctx->M, f.base, ctx->opt.pdas_c, d_active, d_v, s));
+  if (n_active) PFF_TRY(count_bytes(d_active, f.g.n_nodes, ctx->part, n_active, s));
+  return PF_OK;
+}
+
+pf_status pf_transfer(pf_ctx* ctx, int level, int op, const double* d_in, double* d_out, void* stream) {
+  NEED_CTX();
+  if (level < 1 || level >= (int)ctx->lev.size()) {
+    set_error("transfer level must be in [1, n_levels-1]");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!d_in || !d_out || d_in == d_out) {
+    set_error("in/out must be non-NULL and distinct");
+    return PF_ERR_INVALID_ARG;
+  }
+  const Geom& gf = ctx->lev[level].g;
+  const Geom& gc = ctx->lev[level - 1].g;
+  hipStream_t s = st(stream);
+  if (op == 0) return restrict_vec<double, double>(gc, gf, d_in, d_out, nullptr, s);
+  if (op == 1) return prolong_vec<double, double>(gc, gf, d_in, d_out, nullptr, 0, s);
+  if (op == 2) return inject<double>(gc, gf, d_in, d_out, gf.d + 1, s);
+  set_error("op must be 0 (restrict), 1 (prolong) or 2 (inject)");
+  return PF_ERR_INVALID_ARG;
+}
+
+pf_status pf_get_eig_bounds(pf_ctx* ctx, int level, double out[4]) {
+  NEED_CTX();
+  NEED_LEVEL(level);
+  if (!out) {
+    set_error("out is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < 4; ++k) out[k] = ctx->lev[level].eig[k];
+  return PF_OK;
+}
+
+pf_status pf_set_eig_bounds(pf_ctx* ctx, int level, const double in[4]) {
+  NEED_CTX();
+  NEED_LEVEL(level);
+  LevelBuf& b = ctx->lev[level];
+  if (!in) {
+    b.eig_fixed = false;
+    return PF_OK;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (!(in[k] > 0.0) || !std::isfinite(in[k])) {
+      set_error("eigenvalue bounds must be positive and finite");
+      return PF_ERR_INVALID_ARG;
+    }
+  if (in[0] > in[1] || in[2] > in[3]) {
+    set_error("need lam_min <= lam_max per block");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < 4; ++k) b.eig[k] = in[k];
+  b.eig_fixed = true;
+  return PF_OK;
+}
+
+pf_status pf_vcycle(pf_ctx* ctx, int prec, const double* d_r, double* d_z, void* stream) {
+  NEED_CTX();
+  NEED_LIN();
+  if (prec != PF_F64 && prec != PF_F32) {
+    set_error("prec must be PF_F64 or PF_F32");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!d_r || !d_z || d_r == d_z) {
+    set_error("r and z must be non-NULL and distinct");
+    return PF_ERR_INVALID_ARG;
+  }
+  return vcycle(ctx, prec, d_r, d_z, st(stream));
+}
+
+pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde,
+                         pf_newton_report* rep, void* stream) {
+  NEED_CTX();
+  if (!d_U || !d_U_old || !d_phi_tilde) {
+    set_error("U, U_old and phi_tilde must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = st(stream);
+  const int L = (int)ctx->lev.size() - 1;
+  LevelBuf& f = ctx->lev[L];
+  const Geom& g = f.g;
+  pf_newton_report r;
+  std::memset(&r, 0, sizeof(r));
+  const double t0 = now_s();
+  // 1. residual
+  PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RESID, nullptr, d_U, d_phi_tilde, f.mask, ctx->R, s));
+  double bad = 0;
+  PFF_TRY(count_nonfinite(ctx->R, g.n_dofs, ctx->part, &bad, s));
+  if (bad > 0) {
+    set_error("non-finite residual (check U, U_old, phi_tilde)");
+    if (rep) *rep = r;
+    return PF_ERR_NONFINITE;
+  }
+  const double t1 = now_s();
+  // 2-4. active set, lift, level data
+  PFF_TRY(pdas_decide(g, ctx->R, d_U, d_U_old, ctx->M, f.base, ctx->opt.pdas_c, ctx->active, nullptr, s));
+  PFF_TRY(count_bytes(ctx->active, g.n_nodes, ctx->part, &r.n_active, s));
+  PFF_TRY(build_lift(g, d_U, d_U_old, ctx->active, ctx->dl, s));
+  PFF_TRY(set_linearization(ctx, d_U, d_phi_tilde, ctx->active, s));
+  const double* tlift = nullptr;
+  if (r.n_active > 0) {
+    PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RAW, ctx->dl, f.U, f.phit, f.mask, ctx->t, s));
+    tlift = ctx->t;
+  }
+  PFF_TRY(constrain_rhs(g, ctx->R, tlift, ctx->dl, f.mask, ctx->Rt, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  const double t2 = now_s();
+  // 5. FGMRES from the lift
+  PFF_TRY(vec_copy<double>(ctx->dU, ctx->dl, g.n_dofs, s));
+  int iters = 0;
+  double rel = 0, bn = 0;
+  PFF_TRY(fgmres(ctx, ctx->Rt, ctx->dU, ctx->vprec, &iters, &rel, &bn, s));
+  // 6. update
+  PFF_TRY(vec_axpby<double>(d_U, 1.0, ctx->dU, 1.0, g.n_dofs, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  const double t3 = now_s();
+  r.gmres_iters = iters;
+  r.rel_residual = rel;
+  r.rhs_norm = bn;
+  r.converged = rel <= ctx->opt.gmres_rtol ? 1 : 0;
+  r.t_residual_s = t1 - t0;
+  r.t_setup_s = t2 - t1;
+  r.t_solve_s = t3 - t2;
+  r.t_total_s = t3 - t0;
+  if (rep) *rep = r;
+  if (!r.converged) {
+    set_error("FGMRES reached gmres_max_iter before the tolerance");
+    return PF_ERR_NOT_CONVERGED;
+  }
+  return PF_OK;
+}
+
+pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
+  NEED_CTX();
+  NEED_LEVEL(level);
+  if (!info) {
+    set_error("info is NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  const LevelBuf& b = ctx->lev[level];
+  for (int k = 0; k < 3; ++k) {
+    info->n_cells[k] = b.g.N[k];
+    info->n_nodes_axis[k] = b.g.nn[k];
+    info->h[k] = b.g.h[k];
+  }
+  info->n_nodes = b.g.n_nodes;
+  info->n_dofs = b.g.n_dofs;
+  info->n_active_cells = b.n_active_cells;
+  info->precision = level_prec(ctx, level, ctx->vprec);
+  return PF_OK;
+}
+
+pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec) {
+  NEED_CTX();
+  if (prec != PF_F64 && prec != PF_F32) {
+    set_error("prec must be PF_F64 or PF_F32");
+    return PF_ERR_INVALID_ARG;
+  }
+  ctx->vprec = prec;
+  return PF_OK;
+}
+
+}  // extern "C"

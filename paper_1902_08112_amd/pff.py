@@ -1,0 +1,374 @@
+"""ctypes binding of libpff.so (the C ABI declared in include/pff.h).
+
+Argument marshalling only: every computation runs in the HIP library.  The
+pf_* functions mirror the C entry points one to one (pointers are Python ints);
+``Solver`` is a small convenience wrapper that keeps a torch-allocated
+workspace and passes tensor data pointers and the current HIP stream.
+The library must be built (``python -m paper_1902_08112_amd.build``); loading
+fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpff.so")
+
+PF_OK, PF_ERR_INVALID_ARG, PF_ERR_UNSUPPORTED, PF_ERR_DEVICE = 0, 1, 2, 3
+PF_ERR_WORKSPACE, PF_ERR_NOT_CONVERGED, PF_ERR_NONFINITE = 4, 5, 6
+PF_F64, PF_F32 = 0, 1
+PF_BOX, PF_LSHAPE = 0, 1
+PF_MASK_PHI = 8
+
+
+class PffError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("degree", C.c_int), ("n_cells", C.c_int * 3), ("extent", C.c_double * 3),
+                ("domain", C.c_int), ("n_levels", C.c_int), ("dirichlet_faces", C.c_uint)]
+
+
+class Options(C.Structure):
+    _fields_ = [("vcycle_precision", C.c_int), ("cheb_degree", C.c_int), ("cheb_ratio", C.c_double),
+                ("cheb_safety", C.c_double), ("eig_cg_steps", C.c_int), ("coarse_degree", C.c_int),
+                ("coarse_sweeps", C.c_int), ("coarse_lo_factor", C.c_double), ("gmres_restart", C.c_int),
+                ("gmres_max_iter", C.c_int), ("gmres_rtol", C.c_double), ("pdas_c", C.c_double),
+                ("eig_seed", C.c_uint64)]
+
+
+class NewtonReport(C.Structure):
+    _fields_ = [("gmres_iters", C.c_int), ("converged", C.c_int), ("rel_residual", C.c_double),
+                ("rhs_norm", C.c_double), ("n_active", C.c_int64), ("t_residual_s", C.c_double),
+                ("t_setup_s", C.c_double), ("t_solve_s", C.c_double), ("t_total_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n_cells", C.c_int * 3), ("n_nodes_axis", C.c_int * 3), ("n_nodes", C.c_int64),
+                ("n_dofs", C.c_int64), ("n_active_cells", C.c_int64), ("h", C.c_double * 3),
+                ("precision", C.c_int)]
+
+
+_lib = None
+VP, I, D, I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+SIGNATURES = {
+    "pf_default_options": (None, [C.POINTER(Options)]),
+    "pf_workspace_size": (I, [C.POINTER(Mesh), C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    "pf_setup": (I, [C.POINTER(Mesh), D, D, D, D, D, D, C.POINTER(Options), VP, C.c_size_t, VP, C.POINTER(VP)]),
+    "pf_set_constraints": (I, [VP, VP, VP]),
+    "pf_set_linearization": (I, [VP, VP, VP, VP, VP]),
+    "pf_jacobian_apply": (I, [VP, I, I, VP, VP, VP]),
+    "pf_block_apply": (I, [VP, I, I, VP, VP, VP]),
+    "pf_residual": (I, [VP, VP, VP, VP, VP]),
+    "pf_get_diagonal": (I, [VP, I, VP, VP]),
+    "pf_get_lumped_mass": (I, [VP, VP, VP]),
+    "pf_get_level_data": (I, [VP, I, VP, VP, VP, VP]),
+    "pf_active_set": (I, [VP, VP, VP, VP, VP, VP, C.POINTER(I64), VP]),
+    "pf_transfer": (I, [VP, I, I, VP, VP, VP]),
+    "pf_get_eig_bounds": (I, [VP, I, C.POINTER(D)]),
+    "pf_set_eig_bounds": (I, [VP, I, C.POINTER(D)]),
+    "pf_vcycle": (I, [VP, I, VP, VP, VP]),
+    "pf_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
+    "pf_get_level_info": (I, [VP, I, C.POINTER(LevelInfo)]),
+    "pf_set_vcycle_precision": (I, [VP, I]),
+    "pf_destroy": (None, [VP]),
+    "pf_status_string": (C.c_char_p, [I]),
+    "pf_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libpff.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1902_08112_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(SIGNATURES)
+
+
+def _check(status, what):
+    if status != PF_OK:
+        L = lib()
+        raise PffError(status, f"{what}: {L.pf_status_string(status).decode()}: {L.pf_last_error().decode()}")
+
+
+def check(status, what="pff"):
+    _check(status, what)
+    return status
+
+
+# --------------------------------------------------------------------------
+# one-to-one wrappers of the C entry points (pointers as ints)
+# --------------------------------------------------------------------------
+def pf_default_options():
+    o = Options()
+    lib().pf_default_options(C.byref(o))
+    return o
+
+
+def pf_workspace_size(mesh: Mesh, opt: Options = None) -> int:
+    n = C.c_size_t(0)
+    _check(lib().pf_workspace_size(C.byref(mesh), C.byref(opt) if opt else None, C.byref(n)), "pf_workspace_size")
+    return n.value
+
+
+def pf_setup(mesh, E, nu, G_c, eps, kappa, pressure, opt, ws_ptr, ws_bytes, stream=0):
+    out = VP()
+    _check(lib().pf_setup(C.byref(mesh), E, nu, G_c, eps, kappa, pressure, C.byref(opt) if opt else None,
+                          ws_ptr, ws_bytes, stream, C.byref(out)), "pf_setup")
+    return out.value
+
+
+def pf_set_constraints(ctx, bits_ptr, stream=0):
+    _check(lib().pf_set_constraints(ctx, bits_ptr, stream), "pf_set_constraints")
+
+
+def pf_set_linearization(ctx, U_ptr, phit_ptr, active_ptr=None, stream=0):
+    _check(lib().pf_set_linearization(ctx, U_ptr, phit_ptr, active_ptr, stream), "pf_set_linearization")
+
+
+def pf_jacobian_apply(ctx, level, prec, x_ptr, y_ptr, stream=0):
+    _check(lib().pf_jacobian_apply(ctx, level, prec, x_ptr, y_ptr, stream), "pf_jacobian_apply")
+
+
+def pf_block_apply(ctx, level, prec, x_ptr, y_ptr, stream=0):
+    _check(lib().pf_block_apply(ctx, level, prec, x_ptr, y_ptr, stream), "pf_block_apply")
+
+
+def pf_residual(ctx, U_ptr, phit_ptr, R_ptr, stream=0):
+    _check(lib().pf_residual(ctx, U_ptr, phit_ptr, R_ptr, stream), "pf_residual")
+
+
+def pf_get_diagonal(ctx, level, out_ptr, stream=0):
+    _check(lib().pf_get_diagonal(ctx, level, out_ptr, stream), "pf_get_diagonal")
+
+
+def pf_get_lumped_mass(ctx, out_ptr, stream=0):
+    _check(lib().pf_get_lumped_mass(ctx, out_ptr, stream), "pf_get_lumped_mass")
+
+
+def pf_get_level_data(ctx, level, U_ptr, phit_ptr, mask_ptr, stream=0):
+    _check(lib().pf_get_level_data(ctx, level, U_ptr, phit_ptr, mask_ptr, stream), "pf_get_level_data")
+
+
+def pf_active_set(ctx, R_ptr, U_ptr, Uold_ptr, active_ptr, v_ptr=None, want_count=True, stream=0):
+    n = I64(0)
+    _check(lib().pf_active_set(ctx, R_ptr, U_ptr, Uold_ptr, active_ptr, v_ptr,
+                               C.byref(n) if want_count else None, stream), "pf_active_set")
+    return n.value
+
+
+def pf_transfer(ctx, level, op, in_ptr, out_ptr, stream=0):
+    _check(lib().pf_transfer(ctx, level, op, in_ptr, out_ptr, stream), "pf_transfer")
+
+
+def pf_get_eig_bounds(ctx, level):
+    out = (D * 4)()
+    _check(lib().pf_get_eig_bounds(ctx, level, out), "pf_get_eig_bounds")
+    return list(out)
+
+
+def pf_set_eig_bounds(ctx, level, bounds):
+    arr = None if bounds is None else (D * 4)(*bounds)
+    _check(lib().pf_set_eig_bounds(ctx, level, arr), "pf_set_eig_bounds")
+
+
+def pf_vcycle(ctx, prec, r_ptr, z_ptr, stream=0):
+    _check(lib().pf_vcycle(ctx, prec, r_ptr, z_ptr, stream), "pf_vcycle")
+
+
+def pf_newton_step(ctx, U_ptr, Uold_ptr, phit_ptr, stream=0, raise_on_error=True):
+    rep = NewtonReport()
+    st = lib().pf_newton_step(ctx, U_ptr, Uold_ptr, phit_ptr, C.byref(rep), stream)
+    if raise_on_error:
+        _check(st, "pf_newton_step")
+    return st, rep
+
+
+def pf_get_level_info(ctx, level):
+    info = LevelInfo()
+    _check(lib().pf_get_level_info(ctx, level, C.byref(info)), "pf_get_level_info")
+    return info
+
+
+def pf_set_vcycle_precision(ctx, prec):
+    _check(lib().pf_set_vcycle_precision(ctx, prec), "pf_set_vcycle_precision")
+
+
+def pf_destroy(ctx):
+    lib().pf_destroy(ctx)
+
+
+def pf_status_string(s):
+    return lib().pf_status_string(s).decode()
+
+
+def pf_last_error():
+    return lib().pf_last_error().decode()
+
+
+# --------------------------------------------------------------------------
+# torch convenience wrapper
+# --------------------------------------------------------------------------
+def make_mesh(dim, degree, n_cells, extent, domain, n_levels, faces) -> Mesh:
+    m = Mesh()
+    m.dim, m.degree = dim, degree
+    nc = list(n_cells) + [1] * (3 - len(n_cells))
+    ex = list(extent) + [1.0] * (3 - len(extent))
+    for k in range(3):
+        m.n_cells[k] = int(nc[k])
+        m.extent[k] = float(ex[k])
+    m.domain, m.n_levels, m.dirichlet_faces = int(domain), int(n_levels), int(faces)
+    return m
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Solver:
+    """Owns a context and its torch-allocated device workspace."""
+
+    def __init__(self, mesh: Mesh, material: dict, opt: Options = None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.mesh = mesh
+        self.opt = opt or pf_default_options()
+        self.ws_bytes = pf_workspace_size(mesh, self.opt)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        m = material
+        self.ctx = pf_setup(mesh, m["E"], m["nu"], m["G_c"], m["eps"], m["kappa"], m["pressure"], self.opt,
+                            aligned, self.ws_bytes, _stream())
+        self.device = device
+        self.levels = [pf_get_level_info(self.ctx, l) for l in range(mesh.n_levels)]
+
+    def close(self):
+        if self.ctx:
+            pf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # helpers -------------------------------------------------------------
+    def n_dofs(self, level=-1):
+        return self.levels[level].n_dofs
+
+    def n_nodes(self, level=-1):
+        return self.levels[level].n_nodes
+
+    def set_constraints(self, bits):
+        pf_set_constraints(self.ctx, _ptr(bits), _stream())
+
+    def set_linearization(self, U, phit, active=None):
+        pf_set_linearization(self.ctx, _ptr(U), _ptr(phit), _ptr(active), _stream())
+
+    def _empty(self, n, dtype):
+        return self.torch.empty(n, dtype=dtype, device=self.device)
+
+    def jacobian_apply(self, level, x, out=None):
+        prec = PF_F64 if x.dtype == self.torch.float64 else PF_F32
+        y = out if out is not None else self._empty(x.numel(), x.dtype)
+        pf_jacobian_apply(self.ctx, level % len(self.levels), prec, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def block_apply(self, level, x, out=None):
+        prec = PF_F64 if x.dtype == self.torch.float64 else PF_F32
+        y = out if out is not None else self._empty(x.numel(), x.dtype)
+        pf_block_apply(self.ctx, level % len(self.levels), prec, x.data_ptr(), y.data_ptr(), _stream())
+        return y
+
+    def residual(self, U, phit):
+        R = self._empty(U.numel(), self.torch.float64)
+        pf_residual(self.ctx, U.data_ptr(), phit.data_ptr(), R.data_ptr(), _stream())
+        return R
+
+    def diagonal(self, level):
+        lv = level % len(self.levels)
+        out = self._empty(self.levels[lv].n_dofs, self.torch.float64)
+        pf_get_diagonal(self.ctx, lv, out.data_ptr(), _stream())
+        return out
+
+    def lumped_mass(self):
+        out = self._empty(self.n_nodes(), self.torch.float64)
+        pf_get_lumped_mass(self.ctx, out.data_ptr(), _stream())
+        return out
+
+    def level_data(self, level):
+        lv = level % len(self.levels)
+        info = self.levels[lv]
+        U = self._empty(info.n_dofs, self.torch.float64)
+        pt = self._empty(info.n_nodes, self.torch.float64)
+        mk = self._empty(info.n_nodes, self.torch.uint8)
+        pf_get_level_data(self.ctx, lv, U.data_ptr(), pt.data_ptr(), mk.data_ptr(), _stream())
+        return U, pt, mk
+
+    def active_set(self, R, U, Uold):
+        act = self._empty(self.n_nodes(), self.torch.uint8)
+        v = self._empty(self.n_nodes(), self.torch.float64)
+        n = pf_active_set(self.ctx, R.data_ptr(), U.data_ptr(), Uold.data_ptr(), act.data_ptr(), v.data_ptr(),
+                          True, _stream())
+        return act, v, n
+
+    def transfer(self, level, op, x):
+        lv = level % len(self.levels)
+        n_out = self.levels[lv - 1].n_dofs if op in (0, 2) else self.levels[lv].n_dofs
+        out = self._empty(n_out, self.torch.float64)
+        pf_transfer(self.ctx, lv, op, x.data_ptr(), out.data_ptr(), _stream())
+        return out
+
+    def eig_bounds(self, level):
+        return pf_get_eig_bounds(self.ctx, level % len(self.levels))
+
+    def set_eig_bounds(self, level, bounds):
+        pf_set_eig_bounds(self.ctx, level % len(self.levels), bounds)
+
+    def vcycle(self, r, prec=PF_F64):
+        z = self._empty(r.numel(), self.torch.float64)
+        pf_vcycle(self.ctx, prec, r.data_ptr(), z.data_ptr(), _stream())
+        return z
+
+    def newton_step(self, U, Uold, phit, raise_on_error=True):
+        st, rep = pf_newton_step(self.ctx, U.data_ptr(), Uold.data_ptr(), phit.data_ptr(), _stream(),
+                                 raise_on_error)
+        return st, rep
+
+    def set_vcycle_precision(self, prec):
+        pf_set_vcycle_precision(self.ctx, prec)
+
+
+def solver_from_spec(s, device="cuda", **opt_overrides):
+    """Build a Solver for a workload dict from the workloads module."""
+    mesh = make_mesh(s["dim"], s["degree"], s["n_cells"], s["extent"], s["domain"], s["n_levels"], s["faces"])
+    opt = pf_default_options()
+    opt.vcycle_precision = PF_F32 if s.get("vcycle") == "f32" else PF_F64
+    for k, v in opt_overrides.items():
+        setattr(opt, k, v)
+    return Solver(mesh, s["material"], opt, device)

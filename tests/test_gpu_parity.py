@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerances: FP64 operators agree with the oracle to 1e-12 relative (normwise,
+and per block); FP32 operators to 2e-6 relative (FP32 rounding of O(1e2)
+terms); masks, injected data and active sets bit-exact (active sets outside
+the rounding band |v| <= 1e-10 max|v|).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import (EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, mask_to_dofs, oracle_hierarchy,
+                        rel_err)
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+APPLY_CASES = ["tiny2d", "tiny2d_q2", "tiny3d", "tiny3d_q2", "small2d", "small3d", "small3d_q2", "small_lshape",
+               "cfg1_2d_q1_32"]
+
+
+def setup_case(name, seed=1, active_frac=0.1):
+    print(f"[case] {name} seed={seed}", flush=True)
+    s = W.config(name)
+    U, phit = W.random_linearization(s, seed)
+    act = W.random_active(s, seed + 1, active_frac)
+    H = oracle_hierarchy(s)
+    H.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+    S = gpu_solver(s)
+    S.set_linearization(dev(U), dev(phit), dev(act))
+    return s, U, phit, act, H, S
+
+
+@pytest.mark.parametrize("name", APPLY_CASES)
+def test_apply_f64_all_levels(name):
+    s, U, phit, act, H, S = setup_case(name)
+    torch = __import__("torch")
+    for l in range(s["n_levels"]):
+        n = H.levels[l].n_dofs
+        x = np.random.default_rng(100 + l).uniform(-1, 1, n)
+        ref = H.mg[l].G @ x
+        y = host(S.jacobian_apply(l, dev(x)))
+        torch.cuda.synchronize()
+        e = rel_err(y, ref)
+        be = block_rel_errs(y, ref, H.levels[l].n_nodes, s["dim"])
+        print(f"  level {l}: rel {e:.2e} per block {be}", flush=True)
+        assert e <= 1e-12 and max(be.values()) <= 1e-12
+        # constrained rows are the identity
+        c = H.mg[l].constrained
+        assert np.array_equal(y[c], x[c])
+
+
+@pytest.mark.parametrize("name", APPLY_CASES)
+def test_block_apply_f64(name):
+    s, U, phit, act, H, S = setup_case(name, seed=3)
+    l = s["n_levels"] - 1
+    x = np.random.default_rng(7).uniform(-1, 1, H.levels[l].n_dofs)
+    ref = H.mg[l].B @ x
+    y = host(S.block_apply(l, dev(x)))
+    assert rel_err(y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny3d", "small2d", "small3d_q2", "small_lshape"])
+def test_apply_f32(name):
+    s, U, phit, act, H, S = setup_case(name, seed=5)
+    torch = __import__("torch")
+    for l in range(s["n_levels"]):
+        x = np.random.default_rng(200 + l).uniform(-1, 1, H.levels[l].n_dofs)
+        ref = H.mg[l].G @ x
+        y = host(S.jacobian_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+        e = rel_err(y, ref)
+        print(f"  level {l}: FP32 rel {e:.2e}", flush=True)
+        assert e <= 2e-6
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d_q2", "small3d", "small_lshape", "cfg1_2d_q1_32"])
+def test_residual_f64(name):
+    s, U, phit, act, H, S = setup_case(name, seed=11)
+    fine = H.fine
+    ref = -model.assemble_residual(fine, H.mat, U, phit)
+    R = host(S.residual(dev(U), dev(phit)))
+    assert rel_err(R, ref) <= 1e-12
+    assert max(block_rel_errs(R, ref, fine.n_nodes, s["dim"]).values()) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["tiny2d_q2", "tiny3d", "small3d_q2", "small_lshape"])
+def test_diagonal_and_level_data(name):
+    s, U, phit, act, H, S = setup_case(name, seed=13)
+    d = s["dim"]
+    for l in range(s["n_levels"]):
+        diag = host(S.diagonal(l))
+        ref = H.mg[l].D
+        assert rel_err(diag, ref) <= 1e-12, l
+        Ul, pl, mk = S.level_data(l)
+        assert np.array_equal(host(Ul), H.mg[l].U)      # injection is a copy: bit-exact
+        assert np.array_equal(host(pl), H.mg[l].phit)
+        assert np.array_equal(mask_to_dofs(host(mk), d), H.mg[l].constrained)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d_q2", "small_lshape"])
+def test_lumped_mass(name):
+    s, U, phit, act, H, S = setup_case(name)
+    M = host(S.lumped_mass())
+    assert rel_err(M, model.lumped_mass(H.fine)) <= 1e-14
+
+
+@pytest.mark.parametrize("name", ["tiny2d_q2", "small3d", "small3d_q2"])
+def test_transfers(name):
+    from oracle import mg
+    s, U, phit, act, H, S = setup_case(name)
+    for l in range(1, s["n_levels"]):
+        cf, ff = H.levels[l - 1], H.levels[l]
+        P = mg.prolongation(cf, ff)
+        xf = np.random.default_rng(l).uniform(-1, 1, ff.n_dofs)
+        xc = np.random.default_rng(50 + l).uniform(-1, 1, cf.n_dofs)
+        assert rel_err(host(S.transfer(l, 0, dev(xf))), P.T @ xf) <= 1e-14
+        assert rel_err(host(S.transfer(l, 1, dev(xc))), P @ xc) <= 1e-14
+        inj = mg.inject_nodal(cf, ff, xf, s["dim"] + 1)
+        assert np.array_equal(host(S.transfer(l, 2, dev(xf))), inj)
+
+
+@pytest.mark.parametrize("name", ["cfg1_2d_q1_32", "small3d_q2", "small_lshape"])
+def test_active_set(name):
+    from oracle import newton
+    print(f"[case] active set {name}", flush=True)
+    s = W.config(name)
+    H = oracle_hierarchy(s)
+    U, Uold, phit = W.make_state(s)
+    act_ref, v_ref, R_ref = newton.active_set(H.fine, H.mat, U, Uold, phit)
+    S = gpu_solver(s)
+    R = S.residual(dev(U), dev(phit))
+    act, v, n = S.active_set(R, dev(U), dev(Uold))
+    v = host(v)
+    act = host(act).astype(bool)
+    assert rel_err(v, v_ref) <= 1e-11
+    band = np.abs(v_ref) <= 1e-10 * np.abs(v_ref).max()
+    assert np.array_equal(act[~band], act_ref[~band])
+    print(f"  |A| = {n} (oracle {act_ref.sum()}), excluded ties {band.sum()}", flush=True)
+    assert abs(n - act_ref.sum()) <= band.sum()
+
+
+@pytest.mark.parametrize("name", ["small2d", "tiny3d_q2", "small_lshape"])
+def test_eigenvalue_estimates(name):
+    s, U, phit, act, H, S = setup_case(name, seed=17)
+    H.set_linearization(U, phit, act)       # oracle CG-Lanczos with the same SplitMix64 start vectors
+    for l in range(s["n_levels"]):
+        got = S.eig_bounds(l)
+        e = H.mg[l].eig
+        ref = [e["u"][0], e["u"][1], e["phi"][0], e["phi"][1]]
+        print(f"  level {l}: gpu {np.round(got, 6)} oracle {np.round(ref, 6)}", flush=True)
+        assert np.allclose(got, ref, rtol=1e-8)
+
+
+@pytest.mark.parametrize("name", ["small2d", "tiny3d_q2", "small3d", "small_lshape"])
+def test_vcycle_f64_matches_oracle(name):
+    s, U, phit, act, H, S = setup_case(name, seed=19)
+    bounds = []
+    for l in range(s["n_levels"]):
+        b = S.eig_bounds(l)
+        bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
+    H.set_linearization(U, phit, act, eig_bounds=bounds)
+    r = np.random.default_rng(23).uniform(-1, 1, H.fine.n_dofs)
+    z_ref = H.vcycle(r)
+    z = host(S.vcycle(dev(r)))
+    e = rel_err(z, z_ref)
+    print(f"  vcycle rel {e:.2e}", flush=True)
+    assert e <= 1e-11
+    from paper_1902_08112_amd import PF_F32
+    z32 = host(S.vcycle(dev(r), PF_F32))
+    e32 = rel_err(z32, z_ref)
+    print(f"  vcycle FP32 levels rel {e32:.2e}", flush=True)
+    assert e32 <= 1e-4
+
+
+@pytest.mark.parametrize("name,prec", [("cfg1_2d_q1_32", "f64"), ("cfg1_2d_q1_32", "f32"), ("small3d", "f64"),
+                                       ("small3d_q2", "f32"), ("small_lshape", "f32")])
+def test_newton_step_matches_oracle(name, prec):
+    from oracle import newton
+    print(f"[case] newton {name} {prec}", flush=True)
+    s = dict(W.config(name))
+    s["vcycle"] = prec
+    U, Uold, phit = W.make_state(s)
+    H = oracle_hierarchy(s)
+    ref = newton.newton_step(H, U, Uold, phit)
+    S = gpu_solver(s)
+    Ud = dev(U)
+    st, rep = S.newton_step(Ud, dev(Uold), dev(phit))
+    Un = host(Ud)
+    dU = Un - U
+    e = rel_err(dU, ref["dU"])
+    print(f"  gmres {rep.gmres_iters} (oracle {ref['info']['iters']}), rel res {rep.rel_residual:.2e}, "
+          f"|A| {rep.n_active} (oracle {ref['n_active']}), |dU - dU_oracle|/|dU_oracle| = {e:.2e}", flush=True)
+    assert rep.converged and rep.rel_residual <= 1e-8
+    # both solves reach 1e-8 of the same linear system: the solutions agree to ~cond * 1e-8
+    assert e <= 1e-5
+    d, nn = s["dim"], H.fine.n_nodes
+    act = ref["active"]
+    assert np.allclose(Un[d * nn:][act], Uold[d * nn:][act], atol=1e-12)
