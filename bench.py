@@ -1,0 +1,205 @@
+"""Benchmark: seconds per Newton/active-set step and Jacobian-apply throughput on one MI355X.
+
+Workload (default): 3D unit cube, 64^3 Q1 hexahedra (274,625 nodes, 1,098,500
+DoFs), pressurized penny crack of radius 0.2, eps = 2h, seeded uniform(-1e-3,
+1e-3) displacement, 5-level GMG.  A step is one whole Newton step of the
+library (residual, active set, level data, diagonals, eigenvalue estimates,
+FGMRES with the V-cycle to a 1e-8 true relative residual, update), starting
+each time from the same iterate U_k (the reset copy is inside the timed loop).
+
+value = fine-level DoFs per second of Newton steps with the plain FP64 V-cycle
+(the workload's own setting); the FP32-V-cycle step time and the speedup are
+reported beside it.  The roofline entry is the FP64 Jacobian apply on the
+finest level (dominant kernel), timed with HIP events on the stream the
+library launches on.  cpu_baseline: the FP64 oracle's Newton step on a 16^3
+sample of the same workload (same crack, material and eps), one core.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Jacobian-apply DoFs/s + %HBM peak; s/Newton step, FP32 vs FP64 GMG at 1e-8"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+# algorithmic work of one Jacobian apply (per cell flops, per DoF bytes in FP64)
+FLOP_PER_CELL = {(2, 1): 656.0, (3, 1): 2496.0, (3, 2): 12312.0, (2, 2): 2124.0}
+BYTES_PER_DOF_F64 = {2: 8 * 3 + (8 + 1) / 3.0, 3: 8 * 3 + (8 + 1) / 4.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2_3d_q1_64")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    return ap.parse_args()
+
+
+def cpu_baseline(spec, n_sample):
+    """The oracle's Newton step on an n_sample^d version of the workload (one core)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        ctx = None
+    import workloads as W
+    from oracle import mg, model, newton
+    s = dict(spec)
+    s["n_cells"] = (n_sample,) * s["dim"]
+    s["n_levels"] = min(s["n_levels"], 3)
+    mat = model.Material(**s["material"])
+    U, Uold, phit = W.make_state(s)
+    t0 = time.perf_counter()
+    H = mg.Hierarchy(s["dim"], s["degree"], s["n_cells"], s["extent"], s["domain"], s["n_levels"], s["faces"], mat)
+    out = newton.newton_step(H, U, Uold, phit)
+    dt = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.__exit__(None, None, None)
+    nd = H.fine.n_dofs
+    return {"value": nd / dt, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle Newton step (assembly, FGMRES+V-cycle to 1e-8) on the {n_sample}^{s['dim']} "
+                      f"version of the workload ({nd} DoFs, {s['n_levels']} levels), {dt:.1f} s, "
+                      f"{out['info']['iters']} FGMRES iterations; os.cpu_count()={os.cpu_count()}"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the multi-GPU path is a design, "
+              f"not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1902_08112_amd import pff
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    s = W.config(a.workload)
+    U0, Uold, phit = W.make_state(s)
+    S = pff.solver_from_spec(s)
+    bits = W.extra_constraint_bits(s)
+    if bits is not None:
+        S.set_constraints(torch.from_numpy(bits).cuda())
+    n_dofs = S.n_dofs()
+    dU0 = torch.from_numpy(U0).cuda()
+    dUold = torch.from_numpy(Uold).cuda()
+    dphit = torch.from_numpy(phit).cuda()
+    U = torch.empty_like(dU0)
+
+    def run_steps(k, prec):
+        S.set_vcycle_precision(prec)
+        reps = []
+        for _ in range(k):
+            U.copy_(dU0)
+            st, rep = S.newton_step(U, dUold, dphit)
+            reps.append(rep.as_dict())
+        return reps
+
+    base_prec = pff.PF_F32 if s.get("vcycle") == "f32" else pff.PF_F64
+    other_prec = pff.PF_F64 if base_prec == pff.PF_F32 else pff.PF_F32
+    run_steps(a.warmup, base_prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = run_steps(a.steps, base_prec)
+    torch.cuda.synchronize()
+    t_base = (time.perf_counter() - t0) / a.steps
+    run_steps(a.warmup, other_prec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps_o = run_steps(a.steps, other_prec)
+    torch.cuda.synchronize()
+    t_other = (time.perf_counter() - t0) / a.steps
+    t64, t32 = (t_base, t_other) if base_prec == pff.PF_F64 else (t_other, t_base)
+    r64, r32 = (reps, reps_o) if base_prec == pff.PF_F64 else (reps_o, reps)
+
+    # dominant kernel: FP64 Jacobian apply on the finest level (linearization of the last step)
+    x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n_dofs)).cuda()
+    y = torch.empty_like(x)
+    L = s["n_levels"] - 1
+    for _ in range(5):
+        S.jacobian_apply(L, x, out=y)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(a.apply_reps):
+        S.jacobian_apply(L, x, out=y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_apply = ev0.elapsed_time(ev1) / 1e3 / a.apply_reps
+    x32 = x.float()
+    y32 = torch.empty_like(x32)
+    for _ in range(5):
+        S.jacobian_apply(L, x32, out=y32)
+    ev0.record(stream)
+    for _ in range(a.apply_reps):
+        S.jacobian_apply(L, x32, out=y32)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_apply32 = ev0.elapsed_time(ev1) / 1e3 / a.apply_reps
+
+    info = S.levels[L]
+    n_cells = int(info.n_active_cells)
+    flops = FLOP_PER_CELL[(s["dim"], s["degree"])] * n_cells
+    bytes_ = BYTES_PER_DOF_F64[s["dim"]] * n_dofs
+    ach_tf = flops / t_apply / 1e12
+    roof = {"bound": "alu", "achieved": round(ach_tf, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach_tf / FP64_PEAK_TFLOPS, 5), "traffic": None,
+            "kernel": "FP64 Jacobian apply, finest level", "flop_per_launch": flops, "bytes_per_launch": bytes_,
+            "hbm_achieved_GBs": round(bytes_ / t_apply / 1e9, 2),
+            "hbm_frac": round(bytes_ / t_apply / 1e9 / HBM_PEAK_GBS, 5),
+            "apply_s": t_apply, "apply_f32_s": t_apply32}
+
+    out = {
+        "metric": METRIC,
+        "value": n_dofs / (t64 if base_prec == pff.PF_F64 else t32),
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * t_base,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": a.workload, "dim": s["dim"], "degree": s["degree"], "n_cells": list(s["n_cells"]),
+                   "n_levels": s["n_levels"], "dofs": n_dofs,
+                   "vcycle": "f64" if base_prec == pff.PF_F64 else "f32", "gmres_rtol": 1e-8},
+        "newton_s_fp64": t64,
+        "newton_s_fp32_vcycle": t32,
+        "fp32_vcycle_speedup": t64 / t32,
+        "gmres_iters_fp64": r64[-1]["gmres_iters"],
+        "gmres_iters_fp32": r32[-1]["gmres_iters"],
+        "rel_residual_fp64": r64[-1]["rel_residual"],
+        "rel_residual_fp32": r32[-1]["rel_residual"],
+        "n_active": r64[-1]["n_active"],
+        "apply_dofs_per_s_fp64": n_dofs / t_apply,
+        "apply_dofs_per_s_fp32": n_dofs / t_apply32,
+        "stage_s_fp64": {k: r64[-1][k] for k in ("t_residual_s", "t_setup_s", "t_solve_s")},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    S.close()
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, a.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
