@@ -218,6 +218,23 @@ pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const 
 /* Level sizes. */
 pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
 
+/* Autotuner of the Q1 cell loop (the tensor-product apply of Sec. 4.1).  For
+ * every level, precision and operator (mode 0: G~, mode 1: smoother block
+ * B~) it times `reps` applies of each candidate kernel shape with HIP events
+ * on `stream` and keeps the fastest in the context.  Candidates: variant 2 =
+ * one thread per cell with atomic scatter; variant 0 / 1 = one wavefront per
+ * 8x8 / 16x4 tile of cells marching through chunks of zc node planes with
+ * register carries (owner-computes, deterministic).  Requires
+ * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
+ * Q2 levels have one kernel and are skipped. */
+pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
+/* Read / force the choice of one (level, prec, mode); variant -1 = size heuristic,
+ * zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */
+pf_status pf_get_tuning(pf_ctx* ctx, int level, int prec, int mode, int* variant, int* zc);
+pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant, int zc);
+/* JSON text of the choices and measured candidate times (microseconds per apply). */
+pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len);
+
 /* Change the V-cycle precision used by pf_newton_step (PF_F64 or PF_F32). */
 pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec);
 

@@ -282,6 +282,8 @@ CellParams make_cell_params(const Geom& g, const Material& m) {
   cp.pres = m.p;
   cp.gc_over_eps = m.Gc / m.eps;
   cp.gc_eps = m.Gc * m.eps;
+  cp.variant = -1;
+  cp.zc = -1;
   return cp;
 }
 

@@ -1,17 +1,607 @@
-// Tiled Q1 cell loops (fast path); see launch_cell_q1_* below.
+// Tiled owner-computes Q1 cell loops (the fast path of the Jacobian and the
+// smoother operator, Sec. 4.1) for 2D and 3D, FP64 and FP32.
+//
+// One wavefront per tile.  3D: a TX x TY patch of cells (one cell per lane)
+// marches along z through a chunk of node planes; 2D: 64 cells along x march
+// along y.  Each lane owns the node at the lower corner of its cell.  Per
+// cell layer the 2^d corner contributions are combined without atomics:
+// along x with a one-lane shuffle, along y (3D) with a TX-lane shuffle, and
+// along the marching axis with a register carry from the previous layer.
+// Tiles overlap by one cell column in x and y (and one layer per chunk), so a
+// lane with i = 0 or j = 0 computes a halo cell and owns nothing; every node is
+// written exactly once, with plain stores, including the identity rows of the
+// constrained DoFs.  The result is deterministic.
+//
+// The cell work is split into a displacement part (test functions w:
+// g(phi~) sigma(du) : e(w)) and a phase-field part (test functions psi), each
+// sum-factorized with q1_math.h, which keeps the live register set small.
 #include "common.h"
+#include "q1_math.h"
 
 namespace pff {
 
-pf_status launch_cell_q1_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
-                           const uint8_t*, double*, hipStream_t, bool* handled) {
-  *handled = false;
+using q1::grad2;
+using q1::grad2T;
+using q1::grad3;
+using q1::grad3T;
+using q1::val2;
+using q1::val2T;
+using q1::val3;
+using q1::val3T;
+
+template <typename T>
+struct Consts {
+  T mu, lam, kap, pres, gce, gcx, jxw, ih[3];
+  __device__ Consts(const CellParams& cp, int nq) {
+    mu = T(cp.mu);
+    lam = T(cp.lam);
+    kap = T(cp.kappa);
+    pres = T(cp.pres);
+    gce = T(cp.gc_over_eps);
+    gcx = T(cp.gc_eps);
+    jxw = T(cp.vol / nq);
+    ih[0] = T(cp.inv_h[0]);
+    ih[1] = T(cp.inv_h[1]);
+    ih[2] = T(cp.inv_h[2]);
+  }
+};
+
+// ----------------------------------------------------------------------------------- 3D
+// displacement rows of one cell: out[c][a] = sum_q g(phi~) sigma(du):grad(N_a e_c) JxW
+template <typename T>
+__device__ __forceinline__ void cell3_u(const Consts<T>& k, const T du[3][8], const T pt[8], T out[3][8]) {
+  T G[3][3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad3(du[c], k.ih, G[c]);
+  T pq[8];
+  val3(pt, pq);
+  T P[3][3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[c][j][r] = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = q >> 2;
+    const int r0 = qy + 2 * qz, r1 = qx + 2 * qz, r2 = qx + 2 * qy;
+    const T g00 = G[0][0][r0], g01 = G[0][1][r1], g02 = G[0][2][r2];
+    const T g10 = G[1][0][r0], g11 = G[1][1][r1], g12 = G[1][2][r2];
+    const T g20 = G[2][0][r0], g21 = G[2][1][r1], g22 = G[2][2][r2];
+    const T gw = ((T(1) - k.kap) * pq[q] * pq[q] + k.kap) * k.jxw;
+    const T lt = k.lam * (g00 + g11 + g22);
+    const T tm = T(2) * k.mu;
+    const T s00 = gw * (tm * g00 + lt), s11 = gw * (tm * g11 + lt), s22 = gw * (tm * g22 + lt);
+    const T s01 = gw * k.mu * (g01 + g10), s02 = gw * k.mu * (g02 + g20), s12 = gw * k.mu * (g12 + g21);
+    P[0][0][r0] += s00;
+    P[0][1][r1] += s01;
+    P[0][2][r2] += s02;
+    P[1][0][r0] += s01;
+    P[1][1][r1] += s11;
+    P[1][2][r2] += s12;
+    P[2][0][r0] += s02;
+    P[2][1][r1] += s12;
+    P[2][2][r2] += s22;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) out[c][a] = T(0);
+    grad3T(P[c], k.ih, out[c]);
+  }
+}
+
+// phase-field rows: out[a] = sum_q [f(q) N_a + G_c eps grad dphi . grad N_a] JxW
+// f = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) dphi [+ (1-kappa) phi sigma(u):e(du) + 2 p phi div du]
+template <typename T, bool COUPLE>
+__device__ __forceinline__ void cell3_phi(const Consts<T>& k, const T du[3][8], const T dp[8], const T uu[3][8],
+                                          const T ph[8], T out[8]) {
+  T Gu[3][3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) grad3(uu[c], k.ih, Gu[c]);
+  T Gd[3][3][4];
+  T pv[8];
+  if (COUPLE) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) grad3(du[c], k.ih, Gd[c]);
+    val3(ph, pv);
+  }
+  T dv[8];
+  val3(dp, dv);
+  T fv[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int qx = q & 1, qy = (q >> 1) & 1, qz = q >> 2;
+    const int r0 = qy + 2 * qz, r1 = qx + 2 * qz, r2 = qx + 2 * qy;
+    const T e00 = Gu[0][0][r0], e11 = Gu[1][1][r1], e22 = Gu[2][2][r2];
+    const T e01 = T(0.5) * (Gu[0][1][r1] + Gu[1][0][r0]);
+    const T e02 = T(0.5) * (Gu[0][2][r2] + Gu[2][0][r0]);
+    const T e12 = T(0.5) * (Gu[1][2][r2] + Gu[2][1][r1]);
+    const T tru = e00 + e11 + e22;
+    const T ee = e00 * e00 + e11 * e11 + e22 * e22 + T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
+    const T Es = T(0.5) * k.lam * tru * tru + k.mu * ee;
+    const T cphi = (T(1) - k.kap) * Es + T(2) * k.pres * tru + k.gce;
+    T f = cphi * dv[q];
+    if (COUPLE) {
+      const T d00 = Gd[0][0][r0], d11 = Gd[1][1][r1], d22 = Gd[2][2][r2];
+      const T d01 = T(0.5) * (Gd[0][1][r1] + Gd[1][0][r0]);
+      const T d02 = T(0.5) * (Gd[0][2][r2] + Gd[2][0][r0]);
+      const T d12 = T(0.5) * (Gd[1][2][r2] + Gd[2][1][r1]);
+      const T trd = d00 + d11 + d22;
+      const T eed = e00 * d00 + e11 * d11 + e22 * d22 + T(2) * (e01 * d01 + e02 * d02 + e12 * d12);
+      const T sde = T(2) * k.mu * eed + k.lam * tru * trd;
+      f += pv[q] * ((T(1) - k.kap) * sde + T(2) * k.pres * trd);
+    }
+    fv[q] = f * k.jxw;
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) out[a] = T(0);
+  val3T(fv, out);
+  T Gp[3][4];
+  grad3(dp, k.ih, Gp);
+  const T s = T(2) * k.gcx * k.jxw;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gp[j][r] *= s;
+  grad3T(Gp, k.ih, out);
+}
+
+// combine the corner contributions of a TX x TY patch: value at the lane's own node of
+// plane k (layers k-1 and k) and the carry into plane k+1
+template <typename T, int TX>
+__device__ __forceinline__ void combine3(const T out[8], T carry, T& val, T& ncarry) {
+  T X[2][2];
+#pragma unroll
+  for (int az = 0; az < 2; ++az)
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay) X[ay][az] = out[2 * ay + 4 * az] + __shfl_up(out[1 + 2 * ay + 4 * az], 1, TX);
+  const T y0 = X[0][0] + __shfl_up(X[1][0], TX, 64);
+  const T y1 = X[0][1] + __shfl_up(X[1][1], TX, 64);
+  val = y0 + carry;
+  ncarry = y1;
+}
+
+template <typename T, int MODE, int TX, int TY>
+__global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, const T* __restrict__ x,
+                                              const T* __restrict__ U, const T* __restrict__ phit,
+                                              const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  static_assert(TX * TY == 64, "one wavefront per tile");
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int lane = threadIdx.x;
+  const int i = lane % TX, j = lane / TX;
+  const int cx = (int)blockIdx.x * (TX - 1) - 1 + i;
+  const int cy = (int)blockIdx.y * (TY - 1) - 1 + j;
+  const int z_lo = (int)blockIdx.z * zc;
+  const int z_hi = min(z_lo + zc, cp.nn[2]);
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  const bool own_xy = i >= 1 && j >= 1 && cx <= cp.nn[0] - 1 && cy <= cp.nn[1] - 1;
+  const bool cell_xy = cx >= 0 && cx < cp.N[0] && cy >= 0 && cy < cp.N[1] &&
+                       !cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1]);
+  const Consts<T> kc(cp, 8);
+  T carry[4] = {T(0), T(0), T(0), T(0)};
+  for (int kz = z_lo - 1; kz < z_hi; ++kz) {
+    const bool cell = cell_xy && kz >= 0 && kz < cp.N[2];
+    const int64_t g0 = cell ? (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz : 0;
+    int64_t gi[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (a >> 2) * sz;
+    uint8_t mk[8];
+    T du[3][8];
+    T outu[3][8];
+    if (cell) {
+      T pt[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        mk[a] = mask[gi[a]];
+        pt[a] = phit[gi[a]];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T v = x[c * nn + gi[a]];
+          du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+        }
+      }
+      cell3_u<T>(kc, du, pt, outu);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
+    }
+    T val[4], nc[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) combine3<T, TX>(outu[c], carry[c], val[c], nc[c]);
+    T outp[8];
+    if (cell) {
+      T dp[8], uu[3][8], ph[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const T v = x[3 * nn + gi[a]];
+        dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uu[c][a] = U[c * nn + gi[a]];
+        ph[a] = COUPLE ? U[3 * nn + gi[a]] : T(0);
+      }
+      cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) outp[a] = T(0);
+    }
+    combine3<T, TX>(outp, carry[3], val[3], nc[3]);
+    if (own_xy && kz >= z_lo) {
+      const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+      const uint8_t m = mask[go];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t o = c * nn + go;
+        y[o] = (m & mask_bit(c, 3)) ? x[o] : val[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) carry[c] = nc[c];
+  }
+}
+
+// ----------------------------------------------------------------------------------- 2D
+template <typename T>
+__device__ __forceinline__ void cell2_u(const Consts<T>& k, const T du[2][4], const T pt[4], T out[2][4]) {
+  T G[2][2][2];
+  grad2(du[0], k.ih, G[0]);
+  grad2(du[1], k.ih, G[1]);
+  T pq[4];
+  val2(pt, pq);
+  T P[2][2][2] = {{{T(0), T(0)}, {T(0), T(0)}}, {{T(0), T(0)}, {T(0), T(0)}}};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qx = q & 1, qy = q >> 1;
+    const T g00 = G[0][0][qy], g01 = G[0][1][qx], g10 = G[1][0][qy], g11 = G[1][1][qx];
+    const T gw = ((T(1) - k.kap) * pq[q] * pq[q] + k.kap) * k.jxw;
+    const T lt = k.lam * (g00 + g11);
+    const T s00 = gw * (T(2) * k.mu * g00 + lt), s11 = gw * (T(2) * k.mu * g11 + lt);
+    const T s01 = gw * k.mu * (g01 + g10);
+    P[0][0][qy] += s00;
+    P[0][1][qx] += s01;
+    P[1][0][qy] += s01;
+    P[1][1][qx] += s11;
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) out[c][a] = T(0);
+    grad2T(P[c], k.ih, out[c]);
+  }
+}
+
+template <typename T, bool COUPLE>
+__device__ __forceinline__ void cell2_phi(const Consts<T>& k, const T du[2][4], const T dp[4], const T uu[2][4],
+                                          const T ph[4], T out[4]) {
+  T Gu[2][2][2], Gd[2][2][2];
+  grad2(uu[0], k.ih, Gu[0]);
+  grad2(uu[1], k.ih, Gu[1]);
+  T pv[4];
+  if (COUPLE) {
+    grad2(du[0], k.ih, Gd[0]);
+    grad2(du[1], k.ih, Gd[1]);
+    val2(ph, pv);
+  }
+  T dv[4];
+  val2(dp, dv);
+  T fv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int qx = q & 1, qy = q >> 1;
+    const T e00 = Gu[0][0][qy], e11 = Gu[1][1][qx];
+    const T e01 = T(0.5) * (Gu[0][1][qx] + Gu[1][0][qy]);
+    const T tru = e00 + e11;
+    const T Es = T(0.5) * k.lam * tru * tru + k.mu * (e00 * e00 + e11 * e11 + T(2) * e01 * e01);
+    const T cphi = (T(1) - k.kap) * Es + T(2) * k.pres * tru + k.gce;
+    T f = cphi * dv[q];
+    if (COUPLE) {
+      const T d00 = Gd[0][0][qy], d11 = Gd[1][1][qx];
+      const T d01 = T(0.5) * (Gd[0][1][qx] + Gd[1][0][qy]);
+      const T trd = d00 + d11;
+      const T sde = T(2) * k.mu * (e00 * d00 + e11 * d11 + T(2) * e01 * d01) + k.lam * tru * trd;
+      f += pv[q] * ((T(1) - k.kap) * sde + T(2) * k.pres * trd);
+    }
+    fv[q] = f * k.jxw;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) out[a] = T(0);
+  val2T(fv, out);
+  T Gp[2][2];
+  grad2(dp, k.ih, Gp);
+  const T s = T(2) * k.gcx * k.jxw;
+  Gp[0][0] *= s;
+  Gp[0][1] *= s;
+  Gp[1][0] *= s;
+  Gp[1][1] *= s;
+  grad2T(Gp, k.ih, out);
+}
+
+template <typename T>
+__device__ __forceinline__ void combine2(const T out[4], T carry, T& val, T& ncarry) {
+  const T x0 = out[0] + __shfl_up(out[1], 1, 64);
+  const T x1 = out[2] + __shfl_up(out[3], 1, 64);
+  val = x0 + carry;
+  ncarry = x1;
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, const T* __restrict__ x,
+                                              const T* __restrict__ U, const T* __restrict__ phit,
+                                              const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int i = threadIdx.x;
+  const int cx = (int)blockIdx.x * 63 - 1 + i;
+  const int y_lo = (int)blockIdx.y * zc;
+  const int y_hi = min(y_lo + zc, cp.nn[1]);
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1];
+  const bool own_x = i >= 1 && cx <= cp.nn[0] - 1;
+  const bool cell_x = cx >= 0 && cx < cp.N[0];
+  const Consts<T> kc(cp, 4);
+  T carry[3] = {T(0), T(0), T(0)};
+  for (int ky = y_lo - 1; ky < y_hi; ++ky) {
+    const bool cell = cell_x && ky >= 0 && ky < cp.N[1] && !cell_in_hole(cp.lshape, cx, ky, cp.N[0], cp.N[1]);
+    const int64_t g0 = cell ? (int64_t)cx + (int64_t)ky * sy : 0;
+    int64_t gi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gi[a] = g0 + (a & 1) + (a >> 1) * sy;
+    uint8_t mk[4];
+    T du[2][4], outu[2][4];
+    if (cell) {
+      T pt[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        mk[a] = mask[gi[a]];
+        pt[a] = phit[gi[a]];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const T v = x[c * nn + gi[a]];
+          du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+        }
+      }
+      cell2_u<T>(kc, du, pt, outu);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) outu[c][a] = T(0);
+    }
+    T val[3], nc[3];
+    combine2<T>(outu[0], carry[0], val[0], nc[0]);
+    combine2<T>(outu[1], carry[1], val[1], nc[1]);
+    T outp[4];
+    if (cell) {
+      T dp[4], uu[2][4], ph[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const T v = x[2 * nn + gi[a]];
+        dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+        uu[0][a] = U[gi[a]];
+        uu[1][a] = U[nn + gi[a]];
+        ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+      }
+      cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) outp[a] = T(0);
+    }
+    combine2<T>(outp, carry[2], val[2], nc[2]);
+    if (own_x && ky >= y_lo) {
+      const int64_t go = (int64_t)cx + (int64_t)ky * sy;
+      const uint8_t m = mask[go];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t o = c * nn + go;
+        y[o] = (m & mask_bit(c, 2)) ? x[o] : val[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+  }
+}
+
+// ----------------------------------------------------------------------------------- atomic variant
+// One thread per cell with the same sum-factorized cell math; contributions are
+// added with device atomics into y pre-set to Pi_C x.  No halo recompute, so it
+// wins on levels too small to fill the chip with marching tiles.
+template <typename T, int MODE>
+__global__ __launch_bounds__(128) void k_q1_3d_atomic(CellParams cp, const T* __restrict__ x,
+                                                      const T* __restrict__ U, const T* __restrict__ phit,
+                                                      const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cid >= cp.n_cells) return;
+  const int cx = (int)(cid % cp.N[0]);
+  const int cy = (int)((cid / cp.N[0]) % cp.N[1]);
+  const int cz = (int)(cid / ((int64_t)cp.N[0] * cp.N[1]));
+  if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  const int64_t g0 = (int64_t)cx + (int64_t)cy * sy + (int64_t)cz * sz;
+  int64_t gi[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (a >> 2) * sz;
+  const Consts<T> kc(cp, 8);
+  uint8_t mk[8];
+  T du[3][8], pt[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    mk[a] = mask[gi[a]];
+    pt[a] = phit[gi[a]];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T v = x[c * nn + gi[a]];
+      du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+    }
+  }
+  {
+    T outu[3][8];
+    cell3_u<T>(kc, du, pt, outu);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
+  }
+  T dp[8], uu[3][8], ph[8], outp[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T v = x[3 * nn + gi[a]];
+    dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uu[c][a] = U[c * nn + gi[a]];
+    ph[a] = COUPLE ? U[3 * nn + gi[a]] : T(0);
+  }
+  cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    if (!(mk[a] & kMaskPhi)) atomicAdd(&y[3 * nn + gi[a]], outp[a]);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(128) void k_q1_2d_atomic(CellParams cp, const T* __restrict__ x,
+                                                      const T* __restrict__ U, const T* __restrict__ phit,
+                                                      const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cid >= cp.n_cells) return;
+  const int cx = (int)(cid % cp.N[0]);
+  const int cy = (int)(cid / cp.N[0]);
+  if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1];
+  const int64_t g0 = (int64_t)cx + (int64_t)cy * sy;
+  int64_t gi[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) gi[a] = g0 + (a & 1) + (a >> 1) * sy;
+  const Consts<T> kc(cp, 4);
+  uint8_t mk[4];
+  T du[2][4], pt[4], outu[2][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    mk[a] = mask[gi[a]];
+    pt[a] = phit[gi[a]];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const T v = x[c * nn + gi[a]];
+      du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+    }
+  }
+  cell2_u<T>(kc, du, pt, outu);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
+  T dp[4], uu[2][4], ph[4], outp[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const T v = x[2 * nn + gi[a]];
+    dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+    uu[0][a] = U[gi[a]];
+    uu[1][a] = U[nn + gi[a]];
+    ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+  }
+  cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+    if (!(mk[a] & kMaskPhi)) atomicAdd(&y[2 * nn + gi[a]], outp[a]);
+}
+
+// ----------------------------------------------------------------------------------- dispatch
+// Variant per level: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles, 2 = atomic.
+// q1_set_tile forces a variant / z-chunk (tuning and tests); -1 restores the heuristic.
+static int64_t q1_tiles_xy(const Geom& g, int tile) {
+  if (g.d == 2) return (g.nn[0] + 62) / 63;
+  const int tx = tile == 1 ? 16 : 8, ty = 64 / tx;
+  return (int64_t)((g.nn[0] + tx - 2) / (tx - 1)) * ((g.nn[1] + ty - 2) / (ty - 1));
+}
+
+int q1_chunk(const Geom& g, int variant, int requested_zc) {
+  if (requested_zc > 0) return requested_zc;
+  const int64_t tiles = q1_tiles_xy(g, variant);
+  const int nplanes = g.nn[g.d - 1];
+  const int cand[] = {32, 16, 8};
+  for (int z : cand)
+    if (tiles * ((nplanes + z - 1) / z) >= 4096) return z;
+  return 8;
+}
+
+// Size heuristic (the autotuner overrides it per level): marching tiles only
+// where they fill the chip with chunks of >= 8 planes.
+int q1_variant(const Geom& g, int mode, int requested) {
+  if (!(g.p == 1 && (mode == MODE_APPLY || mode == MODE_BLOCK) && (g.d == 2 || g.d == 3))) return -1;
+  if (requested >= 0 && requested < kQ1Variants) return (g.d == 2 && requested == 1) ? 0 : requested;
+  const int nplanes = g.nn[g.d - 1];
+  return q1_tiles_xy(g, 0) * ((nplanes + 7) / 8) >= 4096 ? 0 : 2;
+}
+
+bool q1_tiled_handles(const Geom& g, int mode, int requested) {
+  const int v = q1_variant(g, mode, requested);
+  return v == 0 || v == 1;
+}
+
+template <typename T>
+static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                           const uint8_t* mask, T* y, hipStream_t s) {
+  const int variant = q1_variant(g, mode, cp.variant);
+  if (variant == 2) {
+    const int64_t nb = (g.n_cells + 127) / 128;
+    if (g.d == 3) {
+      if (mode == MODE_APPLY)
+        k_q1_3d_atomic<T, MODE_APPLY><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+      else
+        k_q1_3d_atomic<T, MODE_BLOCK><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+    } else {
+      if (mode == MODE_APPLY)
+        k_q1_2d_atomic<T, MODE_APPLY><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+      else
+        k_q1_2d_atomic<T, MODE_BLOCK><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+    }
+    PFF_CHECK_LAUNCH();
+    return PF_OK;
+  }
+  if (g.d == 3) {
+    const int tile = variant;
+    const int tx = tile == 1 ? 16 : 8;
+    const int64_t ntx = (g.nn[0] + tx - 2) / (tx - 1), nty = (g.nn[1] + 64 / tx - 2) / (64 / tx - 1);
+    const int zc = q1_chunk(g, tile, cp.zc);
+    dim3 grid((unsigned)ntx, (unsigned)nty, (unsigned)((g.nn[2] + zc - 1) / zc));
+    if (tile == 1) {
+      if (mode == MODE_APPLY)
+        k_q1_3d<T, MODE_APPLY, 16, 4><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+      else
+        k_q1_3d<T, MODE_BLOCK, 16, 4><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+    } else {
+      if (mode == MODE_APPLY)
+        k_q1_3d<T, MODE_APPLY, 8, 8><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+      else
+        k_q1_3d<T, MODE_BLOCK, 8, 8><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+    }
+  } else {
+    const int64_t ntx = (g.nn[0] + 62) / 63;
+    const int zc = q1_chunk(g, 0, cp.zc);
+    dim3 grid((unsigned)ntx, (unsigned)((g.nn[1] + zc - 1) / zc), 1);
+    if (mode == MODE_APPLY)
+      k_q1_2d<T, MODE_APPLY><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+    else
+      k_q1_2d<T, MODE_BLOCK><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+  }
+  PFF_CHECK_LAUNCH();
   return PF_OK;
 }
-pf_status launch_cell_q1_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
-                           const uint8_t*, float*, hipStream_t, bool* handled) {
-  *handled = false;
-  return PF_OK;
+
+pf_status launch_cell_q1_d(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
+                           const double* phit, const uint8_t* mask, double* y, hipStream_t s, bool* handled) {
+  *handled = q1_variant(g, mode, cp.variant) >= 0;
+  if (!*handled) return PF_OK;
+  return launch_q1<double>(g, cp, mode, x, U, phit, mask, y, s);
+}
+pf_status launch_cell_q1_f(const Geom& g, const CellParams& cp, int mode, const float* x, const float* U,
+                           const float* phit, const uint8_t* mask, float* y, hipStream_t s, bool* handled) {
+  *handled = q1_variant(g, mode, cp.variant) >= 0;
+  if (!*handled) return PF_OK;
+  return launch_q1<float>(g, cp, mode, x, U, phit, mask, y, s);
 }
 
 }  // namespace pff

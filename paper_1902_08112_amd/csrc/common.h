@@ -69,6 +69,8 @@ struct CellParams {
   double inv_h[3];
   double vol;          // cell volume (JxW = w_q * vol)
   double mu, lam, kappa, pres, gc_over_eps, gc_eps;
+  int variant;         // Q1 cell-loop variant (-1: size heuristic), see cell_q1.hip
+  int zc;              // node planes per marching chunk (<= 0: heuristic)
 };
 
 // Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p.
@@ -96,6 +98,14 @@ enum CellMode {
 template <typename T>
 pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                       const uint8_t* mask, T* y, hipStream_t s);
+
+// Q1 cell-loop variants: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles (both
+// write every node of y themselves), 2 = one thread per cell with atomics (y pre-set).
+constexpr int kQ1Variants = 3;
+int q1_variant(const Geom& g, int mode, int requested);
+bool q1_tiled_handles(const Geom& g, int mode, int requested);
+// marching chunk the tiled kernels use for this level and request
+int q1_chunk(const Geom& g, int variant, int requested_zc);
 
 // ---------------------------------------------------------------------------
 // vector kernels (vec.hip)

@@ -48,7 +48,9 @@ static bool starts_from_constrained(int mode) { return mode == MODE_APPLY || mod
 template <typename T>
 pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                    const uint8_t* mask, T* y, hipStream_t s) {
-  if (starts_from_constrained(mode)) {
+  if (q1_tiled_handles(g, mode, cp.variant)) {
+    // the tiled kernels write every entry, identity rows included
+  } else if (starts_from_constrained(mode)) {
     PFF_TRY(vec_init_constrained<T>(y, x, mask, g.n_nodes, g.d, s));
   } else {
     PFF_TRY(vec_fill<T>(y, T(0), g.n_dofs, s));
@@ -120,6 +122,10 @@ struct LevelBuf {
   double eig[4] = {1, 1, 1, 1};
   bool eig_fixed = false;
   int64_t n_active_cells = 0;
+  // cell-loop choice per [precision][mode APPLY/BLOCK]: variant and marching chunk (-1: heuristic)
+  int variant[2][2] = {{-1, -1}, {-1, -1}};
+  int zc[2][2] = {{-1, -1}, {-1, -1}};
+  double tune_us[2][2][8] = {};  // measured candidates (autotune report)
 };
 
 struct pf_ctx {
@@ -326,7 +332,12 @@ int level_prec(pf_ctx* c, int l, int vprec) { return l == 0 ? PF_F64 : vprec; }
 // ---------------------------------------------------------------------------
 pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s) {
   LevelBuf& b = c->lev[l];
-  const CellParams cp = cparams(c, l);
+  CellParams cp = cparams(c, l);
+  if (mode == MODE_APPLY || mode == MODE_BLOCK) {
+    const int pi = prec == PF_F64 ? 0 : 1, mi = mode == MODE_APPLY ? 0 : 1;
+    cp.variant = b.variant[pi][mi];
+    cp.zc = b.zc[pi][mi];
+  }
   if (prec == PF_F64)
     return apply_op<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s);
   return apply_op<float>(b.g, cp, mode, (const float*)x, b.U32, b.phit32, b.mask, (float*)y, s);
@@ -488,12 +499,11 @@ pf_status estimate_eigs(pf_ctx* c, int l, hipStream_t s) {
   rz0[1] = rz[1];
   bool done[2] = {!(rz0[0] > 0), !(rz0[1] > 0)};
   std::vector<double> al[2], be[2];
-  const CellParams cp = cparams(c, l);
   for (int it = 0; it < c->opt.eig_cg_steps; ++it) {
     for (int k = 0; k < 2; ++k)
       if (!done[k] && (rz[k] <= 0.0 || rz[k] <= 1e-24 * rz0[k])) done[k] = true;
     if (done[0] && done[1]) break;
-    PFF_TRY(apply_op<double>(g, cp, MODE_BLOCK, p, b.U, b.phit, b.mask, Ap, s));
+    PFF_TRY(level_apply(c, l, PF_F64, MODE_BLOCK, p, Ap, s));
     PFF_TRY(dot_blocks(p, Ap, g.n_nodes, g.d, c->part, pAp, s));
     double alpha[2] = {0, 0};
     for (int k = 0; k < 2; ++k) {
@@ -570,14 +580,13 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
   LevelBuf& f = c->lev[L];
   const int64_t n = f.g.n_dofs;
   const int m = c->opt.gmres_restart;
-  const CellParams cp = cparams(c, L);
   double bn2 = 0;
   PFF_TRY(dot_host(b, b, n, c->part, &bn2, s));
   const double bnorm = std::sqrt(bn2);
   *bnorm_out = bnorm;
   const double tol = c->opt.gmres_rtol * bnorm;
   auto true_res = [&](double* beta) -> pf_status {
-    PFF_TRY(apply_op<double>(f.g, cp, MODE_APPLY, x, f.U, f.phit, f.mask, c->t, s));
+    PFF_TRY(level_apply(c, L, PF_F64, MODE_APPLY, x, c->t, s));
     PFF_TRY(vec_sub<double>(c->V, b, c->t, n, s));
     double r2 = 0;
     PFF_TRY(dot_host(c->V, c->V, n, c->part, &r2, s));
@@ -605,7 +614,7 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
       double* zj = c->Z + (int64_t)j * n;
       double* w = c->V + (int64_t)(j + 1) * n;
       PFF_TRY(vcycle(c, vprec, vj, zj, s));
-      PFF_TRY(apply_op<double>(f.g, cp, MODE_APPLY, zj, f.U, f.phit, f.mask, w, s));
+      PFF_TRY(level_apply(c, L, PF_F64, MODE_APPLY, zj, w, s));
       double* h1 = c->dscal;
       double* h2 = c->dscal + 256;
       double* nr = c->dscal + 512;
@@ -1057,6 +1066,148 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
   info->n_dofs = b.g.n_dofs;
   info->n_active_cells = b.n_active_cells;
   info->precision = level_prec(ctx, level, ctx->vprec);
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------------------------- autotuner
+// Candidates of the Q1 cell loop: (variant, chunk).  Variant 1 (16x4 tiles) is 3D only.
+static const int kCand[][2] = {{2, -1}, {0, 8}, {0, 16}, {0, 32}, {1, 8}, {1, 16}, {1, 32}};
+static const int kNCand = 7;
+
+static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  if (b.g.p != 1) return PF_OK;
+  hipEvent_t e0, e1;
+  PFF_HIP(hipEventCreate(&e0));
+  PFF_HIP(hipEventCreate(&e1));
+  pf_status st = PF_OK;
+  for (int pi = 0; pi < 2 && st == PF_OK; ++pi) {
+    const int prec = pi == 0 ? PF_F64 : PF_F32;
+    if (prec == PF_F64)
+      st = vec_fill<double>((double*)b.vb, 1.0, b.g.n_dofs, s);
+    else
+      st = vec_fill<float>((float*)b.vb, 1.0f, b.g.n_dofs, s);
+    for (int mi = 0; mi < 2 && st == PF_OK; ++mi) {
+      const int mode = mi == 0 ? MODE_APPLY : MODE_BLOCK;
+      double best = 1e300;
+      int bv = -1, bz = -1;
+      for (int k = 0; k < kNCand && st == PF_OK; ++k) {
+        if (kCand[k][0] == 1 && b.g.d != 3) {
+          b.tune_us[pi][mi][k] = -1.0;
+          continue;
+        }
+        b.variant[pi][mi] = kCand[k][0];
+        b.zc[pi][mi] = kCand[k][1];
+        for (int w = 0; w < 2 && st == PF_OK; ++w) st = level_apply(c, l, prec, mode, b.vb, b.vt, s);
+        if (st != PF_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) st = PF_ERR_DEVICE;
+        for (int r = 0; r < reps && st == PF_OK; ++r) st = level_apply(c, l, prec, mode, b.vb, b.vt, s);
+        if (st != PF_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          set_error("autotune timing failed");
+          st = PF_ERR_DEVICE;
+          break;
+        }
+        const double us = 1e3 * ms / reps;
+        b.tune_us[pi][mi][k] = us;
+        if (us < best) {
+          best = us;
+          bv = kCand[k][0];
+          bz = kCand[k][1];
+        }
+      }
+      b.variant[pi][mi] = bv;
+      b.zc[pi][mi] = bz;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return st;
+}
+
+pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream) {
+  NEED_CTX();
+  NEED_LIN();
+  if (reps < 1 || reps > 10000) {
+    set_error("reps must be in [1, 10000]");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int l = 0; l < (int)ctx->lev.size(); ++l) PFF_TRY(autotune_level(ctx, l, reps, st(stream)));
+  return PF_OK;
+}
+
+static pf_status tuning_index(pf_ctx* ctx, int level, int prec, int mode, int* pi, int* mi) {
+  NEED_LEVEL(level);
+  if ((prec != PF_F64 && prec != PF_F32) || (mode != 0 && mode != 1)) {
+    set_error("prec must be PF_F64/PF_F32 and mode 0 (Jacobian) or 1 (block)");
+    return PF_ERR_INVALID_ARG;
+  }
+  *pi = prec == PF_F64 ? 0 : 1;
+  *mi = mode;
+  return PF_OK;
+}
+
+pf_status pf_get_tuning(pf_ctx* ctx, int level, int prec, int mode, int* variant, int* zc) {
+  NEED_CTX();
+  int pi, mi;
+  PFF_TRY(tuning_index(ctx, level, prec, mode, &pi, &mi));
+  if (!variant || !zc) {
+    set_error("variant and zc must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  *variant = ctx->lev[level].variant[pi][mi];
+  *zc = ctx->lev[level].zc[pi][mi];
+  return PF_OK;
+}
+
+pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant, int zc) {
+  NEED_CTX();
+  int pi, mi;
+  PFF_TRY(tuning_index(ctx, level, prec, mode, &pi, &mi));
+  if (variant < -1 || variant >= kQ1Variants || zc > 4096) {
+    set_error("variant must be in [-1, 2] and zc <= 4096");
+    return PF_ERR_INVALID_ARG;
+  }
+  ctx->lev[level].variant[pi][mi] = variant;
+  ctx->lev[level].zc[pi][mi] = zc;
+  return PF_OK;
+}
+
+pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len) {
+  NEED_CTX();
+  if (!buf || len == 0) {
+    set_error("buf must be non-NULL with len > 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  std::string o = "{\"levels\": [";
+  for (size_t l = 0; l < ctx->lev.size(); ++l) {
+    const LevelBuf& b = ctx->lev[l];
+    if (l) o += ", ";
+    o += "{\"level\": " + std::to_string(l) + ", \"cells\": " + std::to_string(b.g.n_cells) + ", \"choices\": [";
+    for (int pi = 0; pi < 2; ++pi)
+      for (int mi = 0; mi < 2; ++mi) {
+        if (pi || mi) o += ", ";
+        o += "{\"prec\": \"" + std::string(pi ? "f32" : "f64") + "\", \"mode\": \"" + (mi ? "block" : "jacobian") +
+             "\", \"variant\": " + std::to_string(b.variant[pi][mi]) + ", \"zc\": " + std::to_string(b.zc[pi][mi]) +
+             ", \"us\": [";
+        for (int k = 0; k < kNCand; ++k) {
+          if (k) o += ", ";
+          char tmp[64];
+          snprintf(tmp, sizeof(tmp), "[%d, %d, %.3f]", kCand[k][0], kCand[k][1], b.tune_us[pi][mi][k]);
+          o += tmp;
+        }
+        o += "]}";
+      }
+    o += "]}";
+  }
+  o += "]}";
+  if (o.size() + 1 > len) {
+    set_error("report buffer too small: need " + std::to_string(o.size() + 1));
+    return PF_ERR_INVALID_ARG;
+  }
+  std::memcpy(buf, o.c_str(), o.size() + 1);
   return PF_OK;
 }
 

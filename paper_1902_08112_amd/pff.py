@@ -10,6 +10,7 @@ fails loudly otherwise.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -78,6 +79,10 @@ SIGNATURES = {
     "pf_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
     "pf_get_level_info": (I, [VP, I, C.POINTER(LevelInfo)]),
     "pf_set_vcycle_precision": (I, [VP, I]),
+    "pf_autotune": (I, [VP, I, VP]),
+    "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
+    "pf_set_tuning": (I, [VP, I, I, I, I, I]),
+    "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
     "pf_destroy": (None, [VP]),
     "pf_status_string": (C.c_char_p, [I]),
     "pf_last_error": (C.c_char_p, []),
@@ -210,6 +215,26 @@ def pf_get_level_info(ctx, level):
 
 def pf_set_vcycle_precision(ctx, prec):
     _check(lib().pf_set_vcycle_precision(ctx, prec), "pf_set_vcycle_precision")
+
+
+def pf_autotune(ctx, reps=20, stream=0):
+    _check(lib().pf_autotune(ctx, reps, stream), "pf_autotune")
+
+
+def pf_get_tuning(ctx, level, prec, mode):
+    v, z = I(0), I(0)
+    _check(lib().pf_get_tuning(ctx, level, prec, mode, C.byref(v), C.byref(z)), "pf_get_tuning")
+    return v.value, z.value
+
+
+def pf_set_tuning(ctx, level, prec, mode, variant, zc):
+    _check(lib().pf_set_tuning(ctx, level, prec, mode, variant, zc), "pf_set_tuning")
+
+
+def pf_tuning_report(ctx):
+    buf = C.create_string_buffer(1 << 16)
+    _check(lib().pf_tuning_report(ctx, buf, len(buf)), "pf_tuning_report")
+    return json.loads(buf.value.decode())
 
 
 def pf_destroy(ctx):
@@ -362,6 +387,43 @@ class Solver:
 
     def set_vcycle_precision(self, prec):
         pf_set_vcycle_precision(self.ctx, prec)
+
+    # autotuner ---------------------------------------------------------------
+    def tuning_key(self):
+        m = self.mesh
+        arch = self.torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+        return (f"{arch}|d{m.dim}p{m.degree}|{m.n_cells[0]}x{m.n_cells[1]}x{m.n_cells[2]}|dom{m.domain}"
+                f"|L{m.n_levels}")
+
+    def autotune(self, reps=20, cache_path=None):
+        """Pick the fastest Q1 cell-loop shape per level (needs a linearization point).
+
+        With cache_path, choices are read from / written to a JSON file keyed by
+        GPU architecture and mesh shape.  Returns the tuning report.
+        """
+        key = self.tuning_key()
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key in cache:
+            for ch in cache[key]:
+                pf_set_tuning(self.ctx, ch["level"], ch["prec"], ch["mode"], ch["variant"], ch["zc"])
+            return pf_tuning_report(self.ctx)
+        pf_autotune(self.ctx, reps, _stream())
+        rep = pf_tuning_report(self.ctx)
+        if cache_path:
+            choices = []
+            for lv in rep["levels"]:
+                for ch in lv["choices"]:
+                    choices.append(dict(level=lv["level"], prec=PF_F64 if ch["prec"] == "f64" else PF_F32,
+                                        mode=0 if ch["mode"] == "jacobian" else 1, variant=ch["variant"],
+                                        zc=ch["zc"]))
+            cache[key] = choices
+            os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1)
+        return rep
 
 
 def solver_from_spec(s, device="cuda", **opt_overrides):

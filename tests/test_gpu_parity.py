@@ -50,6 +50,49 @@ def test_apply_f64_all_levels(name):
         assert np.array_equal(y[c], x[c])
 
 
+@pytest.mark.parametrize("name", ["cfg1_2d_q1_32", "small3d", "small_lshape"])
+def test_apply_every_kernel_variant(name):
+    """Each Q1 cell-loop shape the autotuner can pick (atomic, 8x8 / 16x4 marching tiles with
+    full and ragged chunks) matches the oracle, in both operators and precisions."""
+    from paper_1902_08112_amd import pff
+    s, U, phit, act, H, S = setup_case(name, seed=29)
+    torch = __import__("torch")
+    variants = [(2, -1), (0, 8), (0, 3), (0, 1)] + ([(1, 8), (1, 5)] if s["dim"] == 3 else [])
+    for l in range(s["n_levels"]):
+        x = np.random.default_rng(300 + l).uniform(-1, 1, H.levels[l].n_dofs)
+        refG, refB = H.mg[l].G @ x, H.mg[l].B @ x
+        for v, zc in variants:
+            for mode in (0, 1):
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F64, mode, v, zc)
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F32, mode, v, zc)
+            y = host(S.jacobian_apply(l, dev(x)))
+            yb = host(S.block_apply(l, dev(x)))
+            y32 = host(S.jacobian_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+            e, eb, e32 = rel_err(y, refG), rel_err(yb, refB), rel_err(y32, refG)
+            print(f"  level {l} variant {v} zc {zc}: {e:.1e} {eb:.1e} {e32:.1e}", flush=True)
+            assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6
+
+
+def test_autotune_report_and_cache(tmp_path):
+    from paper_1902_08112_amd import pff
+    s, U, phit, act, H, S = setup_case("small3d", seed=31)
+    rep = S.autotune(reps=3, cache_path=str(tmp_path / "tune.json"))
+    assert len(rep["levels"]) == s["n_levels"]
+    for lv in rep["levels"]:
+        for ch in lv["choices"]:
+            assert ch["variant"] in (0, 1, 2)
+            times = [t for v, z, t in ch["us"] if t > 0]
+            assert len(times) >= 4 and min(times) > 0
+    # cached choices are restored without timing
+    S2 = gpu_solver(s)
+    S2.set_linearization(dev(U), dev(phit), dev(act))
+    rep2 = S2.autotune(reps=3, cache_path=str(tmp_path / "tune.json"))
+    for a, b in zip(rep["levels"], rep2["levels"]):
+        assert [c["variant"] for c in a["choices"]] == [c["variant"] for c in b["choices"]]
+    x = np.random.default_rng(5).uniform(-1, 1, H.fine.n_dofs)
+    assert rel_err(host(S2.jacobian_apply(-1, dev(x))), H.mg[-1].G @ x) <= 1e-12
+
+
 @pytest.mark.parametrize("name", APPLY_CASES)
 def test_block_apply_f64(name):
     s, U, phit, act, H, S = setup_case(name, seed=3)
