@@ -97,7 +97,8 @@ def main():
     bits = W.extra_constraint_bits(s)
     if bits is not None:
         S.set_constraints(torch.from_numpy(bits).cuda())
-    n_dofs = S.n_dofs()
+    n_vec = S.n_dofs()                   # stored lattice vector length (hole nodes included)
+    n_dofs = S.levels[-1].n_domain_nodes * (s["dim"] + 1)   # DoFs of the domain
     dU0 = torch.from_numpy(U0).cuda()
     dUold = torch.from_numpy(Uold).cuda()
     dphit = torch.from_numpy(phit).cuda()
@@ -133,7 +134,7 @@ def main():
     r64, r32 = (reps, reps_o) if base_prec == pff.PF_F64 else (reps_o, reps)
 
     # dominant kernel: FP64 Jacobian apply on the finest level (linearization of the last step)
-    x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n_dofs)).cuda()
+    x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n_vec)).cuda()
     y = torch.empty_like(x)
     L = s["n_levels"] - 1
     for _ in range(5):

@@ -115,6 +115,7 @@ typedef struct pf_level_info {
   int64_t n_active_cells;
   double h[3];
   int precision;            /* arithmetic type of this level inside the V-cycle */
+  int64_t n_domain_nodes;   /* lattice nodes that belong to an active cell (hole nodes excluded) */
 } pf_level_info;
 
 typedef struct pf_ctx pf_ctx;
@@ -240,6 +241,48 @@ pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec);
 
 /* Release the context (host memory only; the workspace stays the caller's). */
 void pf_destroy(pf_ctx* ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: n independent instances (own mesh sizes, extents, domains,
+ * Dirichlet faces, materials, linearization points; common dim, degree and
+ * n_levels) advanced together.  Every stage of the Newton step and V-cycle is
+ * one launch over the whole batch, so many small problems fill the GPU.
+ *
+ * Packed layout: on each level the instances' vectors (each in the
+ * single-instance layout above) are concatenated in instance order; instance b
+ * occupies DoFs [dof_offsets[b], dof_offsets[b+1]) and nodes
+ * [node_offsets[b], node_offsets[b+1]) of that level (pf_batch_layout).
+ * ------------------------------------------------------------------------ */
+typedef struct pf_batch pf_batch;
+
+/* Workspace bytes for a batch (same validation as pf_workspace_size per instance;
+ * all instances must share dim, degree and n_levels). */
+pf_status pf_batch_workspace_size(const pf_mesh* meshes, int n, const pf_options* opt, size_t* bytes);
+/* materials: host array of n*6 doubles {E, nu, G_c, eps, kappa, pressure} per
+ * instance (ranges as in pf_setup).  Other arguments as in pf_setup. */
+pf_status pf_batch_setup(const pf_mesh* meshes, const double* materials, int n, const pf_options* opt,
+                         void* d_workspace, size_t ws_bytes, void* stream, pf_batch** out);
+/* Host copies of the packed offsets of one level (n+1 entries each; either may be NULL). */
+pf_status pf_batch_layout(pf_batch* b, int level, int64_t* dof_offsets, int64_t* node_offsets);
+/* Extra displacement constraint bits on the finest level, packed by nodes (see pf_set_constraints). */
+pf_status pf_batch_set_constraints(pf_batch* b, const uint8_t* d_bits, void* stream);
+/* As pf_set_linearization, for every instance at once (packed finest-level vectors). */
+pf_status pf_batch_set_linearization(pf_batch* b, const double* d_U, const double* d_phi_tilde,
+                                     const uint8_t* d_active, void* stream);
+/* y = G~_l x for every instance (packed level-l vectors; FP64 or FP32). */
+pf_status pf_batch_jacobian_apply(pf_batch* b, int level, int prec, const void* d_x, void* d_y, void* stream);
+/* One V-cycle for every instance (packed finest-level FP64 vectors). */
+pf_status pf_batch_vcycle(pf_batch* b, int prec, const double* d_r, double* d_z, void* stream);
+/* Raw Ritz estimates of instance inst on level l (as pf_get_eig_bounds). */
+pf_status pf_batch_get_eig_bounds(pf_batch* b, int level, int inst, double out[4]);
+pf_status pf_batch_set_vcycle_precision(pf_batch* b, int prec);
+/* One Newton/active-set step (Algorithm 1) of every instance; reps: n reports
+ * (may be NULL).  FGMRES advances all unconverged instances in lockstep and
+ * stops each at its own tolerance.  Synchronizes.  PF_ERR_NOT_CONVERGED if any
+ * instance hit gmres_max_iter (all reports filled, U updated). */
+pf_status pf_batch_newton_step(pf_batch* b, double* d_U, const double* d_U_old, const double* d_phi_tilde,
+                               pf_newton_report* reps, void* stream);
+void pf_batch_destroy(pf_batch* b);
 
 const char* pf_status_string(pf_status s);
 /* Message of the last failed call on this thread ("" if none). */

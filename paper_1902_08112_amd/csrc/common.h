@@ -71,6 +71,7 @@ struct CellParams {
   double mu, lam, kappa, pres, gc_over_eps, gc_eps;
   int variant;         // Q1 cell-loop variant (-1: size heuristic), see cell_q1.hip
   int zc;              // node planes per marching chunk (<= 0: heuristic)
+  int d, p;            // dimension and degree
 };
 
 // Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p.

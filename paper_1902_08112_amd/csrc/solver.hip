@@ -122,6 +122,7 @@ struct LevelBuf {
   double eig[4] = {1, 1, 1, 1};
   bool eig_fixed = false;
   int64_t n_active_cells = 0;
+  int64_t n_domain_nodes = 0;
   // cell-loop choice per [precision][mode APPLY/BLOCK]: variant and marching chunk (-1: heuristic)
   int variant[2][2] = {{-1, -1}, {-1, -1}};
   int zc[2][2] = {{-1, -1}, {-1, -1}};
@@ -775,6 +776,11 @@ pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double 
     for (int64_t cy = 0; cy < b.g.N[1]; ++cy)
       for (int64_t cx = 0; cx < b.g.N[0]; ++cx) act += cell_in_hole(b.g.lshape, (int)cx, (int)cy, b.g.N[0], b.g.N[1]) ? 0 : 1;
     b.n_active_cells = act * b.g.N[2];
+    // hole nodes: strictly inside the removed quadrant (all adjacent cells in the hole)
+    int64_t hole = 0;
+    if (b.g.lshape)
+      hole = (int64_t)(b.g.nn[0] - 1 - b.g.p * (b.g.N[0] / 2)) * (b.g.nn[1] - 1 - b.g.p * (b.g.N[1] / 2)) * b.g.nn[2];
+    b.n_domain_nodes = b.g.n_nodes - hole;
     pf_status r = build_base_mask(b.g, mesh->dirichlet_faces, b.base, s);
     if (r == PF_OK) r = vec_copy<uint8_t>(b.mask, b.base, b.g.n_nodes, s);
     if (r != PF_OK) {
@@ -1066,6 +1072,7 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
   info->n_dofs = b.g.n_dofs;
   info->n_active_cells = b.n_active_cells;
   info->precision = level_prec(ctx, level, ctx->vprec);
+  info->n_domain_nodes = b.n_domain_nodes;
   return PF_OK;
 }
 

@@ -54,7 +54,7 @@ class NewtonReport(C.Structure):
 class LevelInfo(C.Structure):
     _fields_ = [("n_cells", C.c_int * 3), ("n_nodes_axis", C.c_int * 3), ("n_nodes", C.c_int64),
                 ("n_dofs", C.c_int64), ("n_active_cells", C.c_int64), ("h", C.c_double * 3),
-                ("precision", C.c_int)]
+                ("precision", C.c_int), ("n_domain_nodes", C.c_int64)]
 
 
 _lib = None
@@ -83,6 +83,18 @@ SIGNATURES = {
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
+    "pf_batch_workspace_size": (I, [C.POINTER(Mesh), I, C.POINTER(Options), C.POINTER(C.c_size_t)]),
+    "pf_batch_setup": (I, [C.POINTER(Mesh), C.POINTER(D), I, C.POINTER(Options), VP, C.c_size_t, VP,
+                           C.POINTER(VP)]),
+    "pf_batch_layout": (I, [VP, I, C.POINTER(I64), C.POINTER(I64)]),
+    "pf_batch_set_constraints": (I, [VP, VP, VP]),
+    "pf_batch_set_linearization": (I, [VP, VP, VP, VP, VP]),
+    "pf_batch_jacobian_apply": (I, [VP, I, I, VP, VP, VP]),
+    "pf_batch_vcycle": (I, [VP, I, VP, VP, VP]),
+    "pf_batch_get_eig_bounds": (I, [VP, I, I, C.POINTER(D)]),
+    "pf_batch_set_vcycle_precision": (I, [VP, I]),
+    "pf_batch_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
+    "pf_batch_destroy": (None, [VP]),
     "pf_destroy": (None, [VP]),
     "pf_status_string": (C.c_char_p, [I]),
     "pf_last_error": (C.c_char_p, []),
@@ -93,6 +105,12 @@ def lib():
     """Load libpff.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # Load torch's HIP runtime first so libpff.so binds to the same runtime
+        # (same soname) as the tensors and streams it is handed.
+        try:
+            import torch  # noqa: F401
+        except ImportError:  # pragma: no cover - the C ABI itself does not need torch
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1902_08112_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -434,3 +452,100 @@ def solver_from_spec(s, device="cuda", **opt_overrides):
     for k, v in opt_overrides.items():
         setattr(opt, k, v)
     return Solver(mesh, s["material"], opt, device)
+
+
+class BatchSolver:
+    """A batch context (pf_batch_*) with its torch-allocated workspace and packed-layout helpers."""
+
+    def __init__(self, specs, opt: Options = None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.specs = list(specs)
+        n = len(self.specs)
+        self.n = n
+        self.meshes = (Mesh * n)(*[make_mesh(s["dim"], s["degree"], s["n_cells"], s["extent"], s["domain"],
+                                             s["n_levels"], s["faces"]) for s in self.specs])
+        mats = []
+        for s in self.specs:
+            m = s["material"]
+            mats += [m["E"], m["nu"], m["G_c"], m["eps"], m["kappa"], m["pressure"]]
+        self.mats = (D * (6 * n))(*mats)
+        self.opt = opt or pf_default_options()
+        nb = C.c_size_t(0)
+        _check(lib().pf_batch_workspace_size(self.meshes, n, C.byref(self.opt), C.byref(nb)),
+               "pf_batch_workspace_size")
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        aligned = (self.ws.data_ptr() + 255) & ~255
+        out = VP()
+        _check(lib().pf_batch_setup(self.meshes, self.mats, n, C.byref(self.opt), aligned, self.ws_bytes,
+                                    _stream(), C.byref(out)), "pf_batch_setup")
+        self.b = out.value
+        self.device = device
+        self.L = self.specs[0]["n_levels"]
+        self.dof_off, self.node_off = [], []
+        for l in range(self.L):
+            do, no = (I64 * (n + 1))(), (I64 * (n + 1))()
+            _check(lib().pf_batch_layout(self.b, l, do, no), "pf_batch_layout")
+            self.dof_off.append(list(do))
+            self.node_off.append(list(no))
+
+    def close(self):
+        if self.b:
+            lib().pf_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # packing -----------------------------------------------------------------
+    def pack(self, arrays, level=-1, nodes=False):
+        """Concatenate per-instance numpy arrays into one device tensor in the packed layout."""
+        import numpy as np
+        off = (self.node_off if nodes else self.dof_off)[level]
+        for b, a in enumerate(arrays):
+            assert a.size == off[b + 1] - off[b], (b, a.size, off[b + 1] - off[b])
+        return self.torch.from_numpy(np.ascontiguousarray(np.concatenate(arrays))).to(self.device)
+
+    def unpack(self, t, level=-1, nodes=False):
+        off = (self.node_off if nodes else self.dof_off)[level]
+        h = t.detach().cpu().numpy()
+        return [h[off[b]:off[b + 1]] for b in range(self.n)]
+
+    # calls -------------------------------------------------------------------
+    def set_constraints(self, bits):
+        _check(lib().pf_batch_set_constraints(self.b, _ptr(bits), _stream()), "pf_batch_set_constraints")
+
+    def set_linearization(self, U, phit, active=None):
+        _check(lib().pf_batch_set_linearization(self.b, _ptr(U), _ptr(phit), _ptr(active), _stream()),
+               "pf_batch_set_linearization")
+
+    def jacobian_apply(self, level, x):
+        prec = PF_F64 if x.dtype == self.torch.float64 else PF_F32
+        y = self.torch.empty_like(x)
+        _check(lib().pf_batch_jacobian_apply(self.b, level % self.L, prec, x.data_ptr(), y.data_ptr(), _stream()),
+               "pf_batch_jacobian_apply")
+        return y
+
+    def vcycle(self, r, prec=PF_F64):
+        z = self.torch.empty_like(r)
+        _check(lib().pf_batch_vcycle(self.b, prec, r.data_ptr(), z.data_ptr(), _stream()), "pf_batch_vcycle")
+        return z
+
+    def eig_bounds(self, level, inst):
+        out = (D * 4)()
+        _check(lib().pf_batch_get_eig_bounds(self.b, level % self.L, inst, out), "pf_batch_get_eig_bounds")
+        return list(out)
+
+    def set_vcycle_precision(self, prec):
+        _check(lib().pf_batch_set_vcycle_precision(self.b, prec), "pf_batch_set_vcycle_precision")
+
+    def newton_step(self, U, Uold, phit, raise_on_error=True):
+        reps = (NewtonReport * self.n)()
+        st = lib().pf_batch_newton_step(self.b, U.data_ptr(), Uold.data_ptr(), phit.data_ptr(), reps, _stream())
+        if raise_on_error:
+            _check(st, "pf_batch_newton_step")
+        return st, [r.as_dict() for r in reps]

@@ -1,0 +1,136 @@
+"""Batched solver (pf_batch_*): parity with the oracle and with the same instances solved one by one.
+
+Tolerances: batched FP64 applies vs oracle 1e-12 per instance and level;
+eigenvalue estimates vs single-instance contexts 1e-8 (same SplitMix64
+streams, different reduction order); Newton steps vs single-instance steps:
+same FGMRES iteration counts (+-1) and |dU - dU_single| <= 1e-6 |dU_single|
+(both solves at 1e-8; the difference is rounding carried through the solve).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import EIG_DUMMY, dev, gpu_solver, host, mask_to_dofs, oracle_hierarchy, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(dim=2, seed=0):
+    rng = np.random.default_rng(seed)
+    specs = []
+    sizes = [8, 16, 24, 32, 16] if dim == 2 else [8, 16, 8]
+    for i, n in enumerate(sizes):
+        if dim == 2:
+            c = rng.uniform(0.3, 0.7, 2)
+            cracks = [("segment", tuple(c - [0.1, 0.02]), tuple(c + [0.1, 0.02]))]
+        else:
+            cracks = [("disc", tuple(rng.uniform(0.4, 0.6, 3)), 0.2)]
+        specs.append(W.spec(f"b{i}", dim, 1, n, 3 if dim == 3 else 4, eps_h=rng.uniform(1, 4),
+                            pressure=float(np.exp(rng.uniform(np.log(1e-4), np.log(1e-2)))), cracks=cracks,
+                            u_amp=1e-3, u_seed=100 + i))
+    return specs
+
+
+def batch_solver(specs, **opt):
+    from paper_1902_08112_amd import pff
+    o = pff.pf_default_options()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    return pff.BatchSolver(specs, o)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_apply_matches_oracle(dim):
+    specs = small_batch(dim, seed=1)
+    print(f"[case] batch apply dim={dim} n={len(specs)}", flush=True)
+    BS = batch_solver(specs, eig_cg_steps=2)
+    Us, pts, acts, Hs = [], [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 10 + b)
+        act = W.random_active(s, 20 + b, 0.1)
+        H = oracle_hierarchy(s)
+        H.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+        Us.append(U), pts.append(phit), acts.append(act), Hs.append(H)
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    torch = __import__("torch")
+    for l in range(BS.L):
+        xs = [np.random.default_rng(30 + b + 7 * l).uniform(-1, 1, Hs[b].levels[l].n_dofs) for b in range(len(specs))]
+        ys = BS.unpack(BS.jacobian_apply(l, BS.pack(xs, level=l)), level=l)
+        ys32 = BS.unpack(BS.jacobian_apply(l, BS.pack(xs, level=l).to(torch.float32)), level=l)
+        for b in range(len(specs)):
+            ref = Hs[b].mg[l].G @ xs[b]
+            e, e32 = rel_err(ys[b], ref), rel_err(ys32[b].astype(np.float64), ref)
+            assert e <= 1e-12 and e32 <= 2e-6, (l, b, e, e32)
+
+
+@pytest.mark.parametrize("dim,prec", [(2, "f64"), (2, "f32"), (3, "f64")])
+def test_batch_newton_matches_single_instances(dim, prec):
+    from paper_1902_08112_amd import pff
+    specs = small_batch(dim, seed=2)
+    for s in specs:
+        s["vcycle"] = prec
+    print(f"[case] batch newton dim={dim} {prec} n={len(specs)}", flush=True)
+    states = [W.make_state(s) for s in specs]
+    BS = batch_solver(specs, vcycle_precision=pff.PF_F32 if prec == "f32" else pff.PF_F64)
+    U = BS.pack([st[0] for st in states])
+    st, reps = BS.newton_step(U, BS.pack([st[1] for st in states]), BS.pack([st[2] for st in states], nodes=True))
+    Ub = BS.unpack(U)
+    eig_b = [[BS.eig_bounds(l, b) for l in range(BS.L)] for b in range(len(specs))]
+    for b, s in enumerate(specs):
+        U0, Uold, phit = states[b]
+        S = gpu_solver(s)
+        Ud = dev(U0)
+        _, rep = S.newton_step(Ud, dev(Uold), dev(phit))
+        dU_single = host(Ud) - U0
+        e = rel_err(Ub[b] - U0, dU_single)
+        print(f"  inst {b}: batch its {reps[b]['gmres_iters']} rel {reps[b]['rel_residual']:.1e} |A| "
+              f"{reps[b]['n_active']}; single its {rep.gmres_iters} |A| {rep.n_active}; dU diff {e:.1e}", flush=True)
+        assert reps[b]["converged"] and reps[b]["rel_residual"] <= 1e-8
+        assert abs(reps[b]["gmres_iters"] - rep.gmres_iters) <= 1
+        assert reps[b]["n_active"] == rep.n_active
+        assert e <= 1e-6
+        for l in range(BS.L):
+            assert np.allclose(eig_b[b][l], S.eig_bounds(l), rtol=1e-8)
+
+
+def test_batch_vcycle_linear_and_masked():
+    specs = small_batch(2, seed=3)
+    BS = batch_solver(specs)
+    Us, pts, acts = [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 50 + b)
+        Us.append(U), pts.append(phit), acts.append(W.random_active(s, 60 + b, 0.1))
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    r1 = [np.random.default_rng(70 + b).uniform(-1, 1, u.size) for b, u in enumerate(Us)]
+    r2 = [np.random.default_rng(80 + b).uniform(-1, 1, u.size) for b, u in enumerate(Us)]
+    z1, z2 = BS.unpack(BS.vcycle(BS.pack(r1))), BS.unpack(BS.vcycle(BS.pack(r2)))
+    z12 = BS.unpack(BS.vcycle(BS.pack([2 * a - 3 * c for a, c in zip(r1, r2)])))
+    for b, s in enumerate(specs):
+        assert rel_err(z12[b], 2 * z1[b] - 3 * z2[b]) <= 1e-12
+        H = oracle_hierarchy(s)
+        c = H.level_constraints(s["n_levels"] - 1, acts[b])
+        assert (z1[b][c] == 0).all()
+
+
+def test_batched_family_64_instances():
+    """The 64-instance 2D family (16^2..256^2): one batched step converges every instance;
+    three instances are checked against single-instance solves."""
+    from paper_1902_08112_amd import pff
+    specs = W.batched_instances(seed=4, count=64)
+    print(f"[case] batched family: {len(specs)} instances, sizes "
+          f"{sorted(s['n_cells'][0] for s in specs)}", flush=True)
+    states = [W.make_state(s) for s in specs]
+    BS = batch_solver(specs, vcycle_precision=pff.PF_F32)
+    U = BS.pack([st[0] for st in states])
+    st, reps = BS.newton_step(U, BS.pack([st[1] for st in states]), BS.pack([st[2] for st in states], nodes=True))
+    its = [r["gmres_iters"] for r in reps]
+    print(f"  total DoFs {BS.dof_off[-1][-1]}, iterations min/max {min(its)}/{max(its)}, "
+          f"t {reps[0]['t_total_s']:.3f} s", flush=True)
+    assert all(r["converged"] and r["rel_residual"] <= 1e-8 for r in reps)
+    Ub = BS.unpack(U)
+    for b in (0, 17, 63):
+        U0, Uold, phit = states[b]
+        S = gpu_solver(specs[b])
+        Ud = dev(U0)
+        S.newton_step(Ud, dev(Uold), dev(phit))
+        assert rel_err(Ub[b] - U0, host(Ud) - U0) <= 1e-6
