@@ -77,12 +77,118 @@ def cpu_baseline(spec, n_sample):
                       f"{out['info']['iters']} FGMRES iterations; os.cpu_count()={os.cpu_count()}"}
 
 
+def run_batch(a):
+    """The 64-instance 2D family (16^2..256^2 Q1, 4 levels each) in one batched Newton step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1902_08112_amd import pff
+
+    torch.cuda.set_device(0)
+    specs = W.batched_instances(seed=4, count=64)
+    states = [W.make_state(s) for s in specs]
+    o = pff.pf_default_options()
+    o.vcycle_precision = pff.PF_F32
+    BS = pff.BatchSolver(specs, o)
+    U0 = BS.pack([st[0] for st in states])
+    Uold = BS.pack([st[1] for st in states])
+    phit = BS.pack([st[2] for st in states], nodes=True)
+    U = torch.empty_like(U0)
+    n_dofs = sum(BS.dof_off[-1][b + 1] - BS.dof_off[-1][b] for b in range(BS.n))
+    n_cells = sum(int(np.prod(s["n_cells"])) for s in specs)
+
+    def steps(k, prec):
+        BS.set_vcycle_precision(prec)
+        reps = None
+        for _ in range(k):
+            U.copy_(U0)
+            _, reps = BS.newton_step(U, Uold, phit)
+        return reps
+
+    res = {}
+    for prec in (pff.PF_F32, pff.PF_F64):
+        steps(max(1, a.warmup), prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = steps(a.steps, prec)
+        torch.cuda.synchronize()
+        res[prec] = ((time.perf_counter() - t0) / a.steps, reps)
+    t32, reps32 = res[pff.PF_F32]
+    t64, _ = res[pff.PF_F64]
+    # the same 64 instances one by one (one context each), FP32 V-cycle
+    seq = 0.0
+    for b, s in enumerate(specs):
+        S = pff.solver_from_spec(s)
+        u0, uo, pt = (torch.from_numpy(x).cuda() for x in states[b])
+        u = u0.clone()
+        S.newton_step(u, uo, pt)
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.newton_step(u, uo, pt)
+        torch.cuda.synchronize()
+        seq += time.perf_counter() - t0
+        S.close()
+    # batched FP64 apply on the finest level of every instance (2D Q1: HBM-bound)
+    BS.set_vcycle_precision(pff.PF_F32)
+    x = BS.pack([np.random.default_rng(b).uniform(-1, 1, st[0].size) for b, st in enumerate(states)])
+    for _ in range(5):
+        BS.jacobian_apply(-1, x)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.apply_reps):
+        BS.jacobian_apply(-1, x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_apply = e0.elapsed_time(e1) / 1e3 / a.apply_reps
+    bytes_ = BYTES_PER_DOF_F64[2] * n_dofs
+    ach = bytes_ / t_apply / 1e9
+    out = {
+        "metric": METRIC, "value": n_dofs / t32, "unit": "DoFs/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * t32, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "batch64_2d_q1", "instances": len(specs), "dofs": n_dofs, "n_levels": 4,
+                   "vcycle": "f32", "gmres_rtol": 1e-8},
+        "newton_s_fp32_vcycle": t32, "newton_s_fp64": t64, "fp32_vcycle_speedup": t64 / t32,
+        "one_by_one_s": seq, "batched_speedup": seq / t32,
+        "gmres_iters_min_max": [min(r["gmres_iters"] for r in reps32), max(r["gmres_iters"] for r in reps32)],
+        "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "batched FP64 Jacobian apply, finest levels of all instances",
+                     "bytes_per_launch": bytes_, "flop_per_launch": FLOP_PER_CELL[(2, 1)] * n_cells,
+                     "apply_s": t_apply},
+        "cpu_baseline": None,
+    }
+    BS.close()
+    if not a.no_cpu:
+        small = [s for s in specs if s["n_cells"][0] <= 24]
+        t0 = time.perf_counter()
+        nd = 0
+        from oracle import mg, model, newton
+        for s in small:
+            mat = model.Material(**s["material"])
+            u, uo, pt = W.make_state(s)
+            H = mg.Hierarchy(s["dim"], s["degree"], s["n_cells"], s["extent"], s["domain"], s["n_levels"],
+                             s["faces"], mat)
+            newton.newton_step(H, u, uo, pt)
+            nd += H.fine.n_dofs
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": nd / dt, "unit": "DoFs/s", "cores": 1, "kind": "oracle",
+                               "sample": f"oracle Newton steps of the {len(small)} instances with <= 24^2 cells "
+                                         f"({nd} DoFs) run one after another, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {a.gpus}); the multi-GPU path is a design, "
               f"not part of this build.", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "batch64":
+        return run_batch(a)
     import numpy as np
     import torch
 

@@ -236,6 +236,12 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
 /* JSON text of the choices and measured candidate times (microseconds per apply). */
 pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len);
 
+/* Graph replay of the V-cycle (default on): the first V-cycle after a change
+ * of level data, eigenvalue bounds or tuning is captured into a hipGraph on a
+ * private stream and replayed on the caller's stream afterwards (pf_vcycle and
+ * the FGMRES of pf_newton_step).  enable = 0 launches every kernel directly. */
+pf_status pf_set_graphs(pf_ctx* ctx, int enable);
+
 /* Change the V-cycle precision used by pf_newton_step (PF_F64 or PF_F32). */
 pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec);
 
@@ -276,6 +282,9 @@ pf_status pf_batch_vcycle(pf_batch* b, int prec, const double* d_r, double* d_z,
 /* Raw Ritz estimates of instance inst on level l (as pf_get_eig_bounds). */
 pf_status pf_batch_get_eig_bounds(pf_batch* b, int level, int inst, double out[4]);
 pf_status pf_batch_set_vcycle_precision(pf_batch* b, int prec);
+/* Graph replay of the batched V-cycle (default on; see pf_set_graphs).  Its
+ * coefficients are read from device memory, so one capture serves every step. */
+pf_status pf_batch_set_graphs(pf_batch* b, int enable);
 /* One Newton/active-set step (Algorithm 1) of every instance; reps: n reports
  * (may be NULL).  FGMRES advances all unconverged instances in lockstep and
  * stops each at its own tolerance.  Synchronizes.  PF_ERR_NOT_CONVERGED if any

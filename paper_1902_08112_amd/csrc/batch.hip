@@ -469,6 +469,20 @@ struct pf_batch {
   double *d_alpha = nullptr, *d_beta = nullptr, *d_y = nullptr;
   bool has_extra = false, has_lin = false;
   std::vector<double> h_coef;  // staging for coefficient uploads (kept alive for async copies)
+  // captured batched V-cycle per precision: every coefficient it uses is read from
+  // device memory, so one capture stays valid for the lifetime of the batch
+  double *vin = nullptr, *vout = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t vgraph[2] = {nullptr, nullptr};
+  hipGraphExec_t vexec[2] = {nullptr, nullptr};
+  bool use_graphs = true;
+  ~pf_batch() {
+    for (int k = 0; k < 2; ++k) {
+      if (vexec[k]) hipGraphExecDestroy(vexec[k]);
+      if (vgraph[k]) hipGraphDestroy(vgraph[k]);
+    }
+    if (cap_stream) hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -607,6 +621,8 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
   double* alpha = cv.take<double>(2 * n);
   double* beta = cv.take<double>(2 * n);
   double* y = cv.take<double>((size_t)n * mr);
+  double* vin = cv.take<double>(nd);
+  double* vout = cv.take<double>(nd);
   (void)d;
   if (c) {
     c->lev = lev;
@@ -625,6 +641,8 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
     c->d_alpha = alpha;
     c->d_beta = beta;
     c->d_y = y;
+    c->vin = vin;
+    c->vout = vout;
   }
   return cv.off + 256;
 }
@@ -814,6 +832,33 @@ pf_status bvcycle(pf_batch* c, int vprec, const double* r, double* z, hipStream_
     k_b_mask_free<float, double><<<bgrid(f.n_dofs), 256, 0, s>>>(v, z, (const float*)f.vx, f.mask);
   PFF_CHECK_LAUNCH();
   return PF_OK;
+}
+
+pf_status bvcycle_graph(pf_batch* c, int vprec, const double* r, double* z, hipStream_t s) {
+  const int k = vprec == PF_F64 ? 0 : 1;
+  const int64_t n = c->lev[c->L - 1].n_dofs;
+  if (!c->vexec[k]) {
+    if (!c->cap_stream) PFF_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    PFF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const pf_status st = bvcycle(c, vprec, c->vin, c->vout, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != PF_OK || e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      if (st == PF_OK) set_error(std::string("batched V-cycle capture: ") + hipGetErrorString(e));
+      return st != PF_OK ? st : PF_ERR_DEVICE;
+    }
+    c->vgraph[k] = g;
+    PFF_HIP(hipGraphInstantiate(&c->vexec[k], g, nullptr, nullptr, 0));
+  }
+  PFF_TRY(vec_copy<double>(c->vin, r, n, s));
+  PFF_HIP(hipGraphLaunch(c->vexec[k], s));
+  PFF_TRY(vec_copy<double>(z, c->vout, n, s));
+  return PF_OK;
+}
+
+pf_status bvcycle_any(pf_batch* c, int vprec, const double* r, double* z, hipStream_t s) {
+  return c->use_graphs ? bvcycle_graph(c, vprec, r, z, s) : bvcycle(c, vprec, r, z, s);
 }
 
 // segmented dots: out[k*nseg + s] = V_k . w over segment s (host copy, synchronizes)
@@ -1026,7 +1071,7 @@ pf_status bfgmres(pf_batch* c, const double* b, double* x, int vprec, std::vecto
       double* vj = c->V + (int64_t)j * n;
       double* zj = c->Z + (int64_t)j * n;
       double* w = c->V + (int64_t)(j + 1) * n;
-      PFF_TRY(bvcycle(c, vprec, vj, zj, s));
+      PFF_TRY(bvcycle_any(c, vprec, vj, zj, s));
       PFF_TRY(bapply(c, L - 1, PF_F64, MODE_APPLY, zj, w, s));
       PFF_TRY(seg_dots(c, c->V, n, j + 1, w, f.d_seg1_lo, f.d_seg1_hi, B, h1, nullptr, s));
       k_b_multi_axpy<<<bgrid(n), 256, 0, s>>>(v, w, c->V, n, j + 1, h1, -1.0);
@@ -1282,7 +1327,7 @@ pf_status pf_batch_vcycle(pf_batch* bt, int prec, const double* d_r, double* d_z
     set_error("bad precision or vectors");
     return PF_ERR_INVALID_ARG;
   }
-  return bvcycle(bt, prec, d_r, d_z, bst(stream));
+  return bvcycle_any(bt, prec, d_r, d_z, bst(stream));
 }
 
 pf_status pf_batch_get_eig_bounds(pf_batch* bt, int level, int inst, double out[4]) {
@@ -1292,6 +1337,12 @@ pf_status pf_batch_get_eig_bounds(pf_batch* bt, int level, int inst, double out[
     return PF_ERR_INVALID_ARG;
   }
   for (int k = 0; k < 4; ++k) out[k] = bt->lev[level].eig[4 * inst + k];
+  return PF_OK;
+}
+
+pf_status pf_batch_set_graphs(pf_batch* bt, int enable) {
+  NEED_BATCH();
+  bt->use_graphs = enable != 0;
   return PF_OK;
 }
 

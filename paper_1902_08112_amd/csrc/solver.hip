@@ -138,6 +138,27 @@ struct pf_ctx {
   uint8_t *extra = nullptr, *active = nullptr;
   double *V = nullptr, *Z = nullptr;
   double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
+  // captured V-cycles per precision (input vin, output vout); invalid after any change of
+  // level data, eigenvalue bounds or kernel tuning
+  double *vin = nullptr, *vout = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t vgraph[2] = {nullptr, nullptr};
+  hipGraphExec_t vexec[2] = {nullptr, nullptr};
+  bool vvalid[2] = {false, false};
+  bool use_graphs = true;
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k) {
+      if (vexec[k]) hipGraphExecDestroy(vexec[k]);
+      if (vgraph[k]) hipGraphDestroy(vgraph[k]);
+      vexec[k] = nullptr;
+      vgraph[k] = nullptr;
+      vvalid[k] = false;
+    }
+  }
+  ~pf_ctx() {
+    drop_graphs();
+    if (cap_stream) hipStreamDestroy(cap_stream);
+  }
   bool has_extra = false, has_lin = false;
   size_t ws_bytes = 0;
   int vprec = PF_F64;
@@ -305,6 +326,8 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
   double* part_md = cv.take<double>((size_t)256 * (mr + 2));
   double* dscal = cv.take<double>(1024);
+  double* vin = cv.take<double>(nd);
+  double* vout = cv.take<double>(nd);
   if (c) {
     c->lev = lev;
     c->M = M;
@@ -320,6 +343,8 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->part = part;
     c->part_md = part_md;
     c->dscal = dscal;
+    c->vin = vin;
+    c->vout = vout;
   }
   return cv.off + 256;
 }
@@ -389,7 +414,7 @@ pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, hipStream_t s) {
   T* x = (T*)b.vx;
   T* r = (T*)b.vr;
   if (x_zero) {
-    PFF_TRY(vec_copy<T>(r, bb, b.g.n_dofs, s));
+    PFF_TRY(vec_sub<T>(r, bb, x, b.g.n_dofs, s));  // x == 0: r = b (a kernel, no memcpy node in graphs)
   } else {
     PFF_TRY(level_apply(c, l, prec, MODE_APPLY, x, b.vt, s));
     PFF_TRY(vec_sub<T>(r, bb, (T*)b.vt, b.g.n_dofs, s));
@@ -411,7 +436,7 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
   PFF_TRY(vec_fill<double>(x, 0.0, b.g.n_dofs, s));
   for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
     if (sw == 0) {
-      PFF_TRY(vec_copy<double>(r, bb, b.g.n_dofs, s));
+      PFF_TRY(vec_sub<double>(r, bb, x, b.g.n_dofs, s));  // x == 0
     } else {
       PFF_TRY(level_apply(c, 0, PF_F64, MODE_APPLY, x, b.vt, s));
       PFF_TRY(vec_sub<double>(r, bb, (double*)b.vt, b.g.n_dofs, s));
@@ -476,6 +501,42 @@ pf_status vcycle(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s
   else
     PFF_TRY(mask_free<float, double>(z, (const float*)f.vx, f.mask, f.g.n_nodes, f.g.d, s));
   return PF_OK;
+}
+
+// The V-cycle has no host decision inside and all its coefficients are fixed
+// until the level data change, so it is captured once into a hipGraph (per
+// precision) on a private stream and replayed on the caller's stream: one
+// launch instead of ~10 per level per smoothing step.
+pf_status vcycle_graph(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
+  const int k = vprec == PF_F64 ? 0 : 1;
+  const int64_t n = c->lev.back().g.n_dofs;
+  if (!c->vvalid[k]) {
+    if (!c->cap_stream) PFF_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    if (c->vexec[k]) hipGraphExecDestroy(c->vexec[k]);
+    if (c->vgraph[k]) hipGraphDestroy(c->vgraph[k]);
+    c->vexec[k] = nullptr;
+    c->vgraph[k] = nullptr;
+    PFF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    const pf_status st = vcycle(c, vprec, c->vin, c->vout, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != PF_OK || e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      if (st == PF_OK) set_error(std::string("V-cycle capture: ") + hipGetErrorString(e));
+      return st != PF_OK ? st : PF_ERR_DEVICE;
+    }
+    c->vgraph[k] = g;
+    PFF_HIP(hipGraphInstantiate(&c->vexec[k], g, nullptr, nullptr, 0));
+    c->vvalid[k] = true;
+  }
+  PFF_TRY(vec_copy<double>(c->vin, r, n, s));
+  PFF_HIP(hipGraphLaunch(c->vexec[k], s));
+  PFF_TRY(vec_copy<double>(z, c->vout, n, s));
+  return PF_OK;
+}
+
+pf_status vcycle_any(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
+  return c->use_graphs ? vcycle_graph(c, vprec, r, z, s) : vcycle(c, vprec, r, z, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +632,7 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
     if (!c->lev[l].eig_fixed) PFF_TRY(estimate_eigs(c, l, s));
   PFF_HIP(hipStreamSynchronize(s));
   c->has_lin = true;
+  c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle
   return PF_OK;
 }
 
@@ -614,7 +676,7 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
       double* vj = c->V + (int64_t)j * n;
       double* zj = c->Z + (int64_t)j * n;
       double* w = c->V + (int64_t)(j + 1) * n;
-      PFF_TRY(vcycle(c, vprec, vj, zj, s));
+      PFF_TRY(vcycle_any(c, vprec, vj, zj, s));
       PFF_TRY(level_apply(c, L, PF_F64, MODE_APPLY, zj, w, s));
       double* h1 = c->dscal;
       double* h2 = c->dscal + 256;
@@ -976,6 +1038,7 @@ pf_status pf_set_eig_bounds(pf_ctx* ctx, int level, const double in[4]) {
   }
   for (int k = 0; k < 4; ++k) b.eig[k] = in[k];
   b.eig_fixed = true;
+  ctx->drop_graphs();
   return PF_OK;
 }
 
@@ -990,7 +1053,7 @@ pf_status pf_vcycle(pf_ctx* ctx, int prec, const double* d_r, double* d_z, void*
     set_error("r and z must be non-NULL and distinct");
     return PF_ERR_INVALID_ARG;
   }
-  return vcycle(ctx, prec, d_r, d_z, st(stream));
+  return vcycle_any(ctx, prec, d_r, d_z, st(stream));
 }
 
 pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde,
@@ -1141,6 +1204,7 @@ pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream) {
     set_error("reps must be in [1, 10000]");
     return PF_ERR_INVALID_ARG;
   }
+  ctx->drop_graphs();
   for (int l = 0; l < (int)ctx->lev.size(); ++l) PFF_TRY(autotune_level(ctx, l, reps, st(stream)));
   return PF_OK;
 }
@@ -1179,6 +1243,7 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
   }
   ctx->lev[level].variant[pi][mi] = variant;
   ctx->lev[level].zc[pi][mi] = zc;
+  ctx->drop_graphs();
   return PF_OK;
 }
 
@@ -1215,6 +1280,13 @@ pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len) {
     return PF_ERR_INVALID_ARG;
   }
   std::memcpy(buf, o.c_str(), o.size() + 1);
+  return PF_OK;
+}
+
+pf_status pf_set_graphs(pf_ctx* ctx, int enable) {
+  NEED_CTX();
+  ctx->use_graphs = enable != 0;
+  if (!ctx->use_graphs) ctx->drop_graphs();
   return PF_OK;
 }
 

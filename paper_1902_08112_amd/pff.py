@@ -80,6 +80,7 @@ SIGNATURES = {
     "pf_get_level_info": (I, [VP, I, C.POINTER(LevelInfo)]),
     "pf_set_vcycle_precision": (I, [VP, I]),
     "pf_autotune": (I, [VP, I, VP]),
+    "pf_set_graphs": (I, [VP, I]),
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
@@ -93,6 +94,7 @@ SIGNATURES = {
     "pf_batch_vcycle": (I, [VP, I, VP, VP, VP]),
     "pf_batch_get_eig_bounds": (I, [VP, I, I, C.POINTER(D)]),
     "pf_batch_set_vcycle_precision": (I, [VP, I]),
+    "pf_batch_set_graphs": (I, [VP, I]),
     "pf_batch_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
     "pf_batch_destroy": (None, [VP]),
     "pf_destroy": (None, [VP]),
@@ -406,6 +408,9 @@ class Solver:
     def set_vcycle_precision(self, prec):
         pf_set_vcycle_precision(self.ctx, prec)
 
+    def set_graphs(self, enable):
+        _check(lib().pf_set_graphs(self.ctx, 1 if enable else 0), "pf_set_graphs")
+
     # autotuner ---------------------------------------------------------------
     def tuning_key(self):
         m = self.mesh
@@ -542,6 +547,9 @@ class BatchSolver:
 
     def set_vcycle_precision(self, prec):
         _check(lib().pf_batch_set_vcycle_precision(self.b, prec), "pf_batch_set_vcycle_precision")
+
+    def set_graphs(self, enable):
+        _check(lib().pf_batch_set_graphs(self.b, 1 if enable else 0), "pf_batch_set_graphs")
 
     def newton_step(self, U, Uold, phit, raise_on_error=True):
         reps = (NewtonReport * self.n)()

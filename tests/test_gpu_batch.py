@@ -112,6 +112,34 @@ def test_batch_vcycle_linear_and_masked():
         assert (z1[b][c] == 0).all()
 
 
+def test_batch_vcycle_graph_replay_matches_eager():
+    from paper_1902_08112_amd import PF_F32, PF_F64
+    specs = small_batch(2, seed=5)
+    BS = batch_solver(specs)
+    Us, pts, acts = [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 90 + b)
+        Us.append(U), pts.append(phit), acts.append(W.random_active(s, 95 + b, 0.1))
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    torch = __import__("torch")
+    r = BS.pack([np.random.default_rng(99 + b).uniform(-1, 1, u.size) for b, u in enumerate(Us)])
+    for prec in (PF_F64, PF_F32):
+        tol = 1e-12 if prec == PF_F64 else 2e-6   # atomic-order rounding of the working precision
+        BS.set_graphs(False)
+        z_eager = host(BS.vcycle(r, prec))
+        BS.set_graphs(True)
+        for rep in range(4):
+            assert rel_err(host(BS.vcycle(r, prec)), z_eager) <= tol
+            BS.jacobian_apply(-1, r)
+            torch.cuda.synchronize()
+    # new linearization: coefficients are device data, so the same capture follows them
+    BS.set_linearization(BS.pack([0.5 * u for u in Us]), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    BS.set_graphs(False)
+    z2 = host(BS.vcycle(r))
+    BS.set_graphs(True)
+    assert rel_err(host(BS.vcycle(r)), z2) <= 1e-12
+
+
 def test_batched_family_64_instances():
     """The 64-instance 2D family (16^2..256^2): one batched step converges every instance;
     three instances are checked against single-instance solves."""

@@ -215,6 +215,37 @@ def test_vcycle_f64_matches_oracle(name):
     assert e32 <= 1e-4
 
 
+@pytest.mark.parametrize("name", ["small2d", "small3d", "small3d_q2"])
+def test_vcycle_graph_replay_matches_eager(name):
+    """The captured V-cycle, replayed several times with eager work and synchronizations in between,
+    gives the eager V-cycle's result every time (both precisions)."""
+    from paper_1902_08112_amd import PF_F32, PF_F64
+    s, U, phit, act, H, S = setup_case(name, seed=37)
+    torch = __import__("torch")
+    n = H.fine.n_dofs
+    r = dev(np.random.default_rng(41).uniform(-1, 1, n))
+    for prec in (PF_F64, PF_F32):
+        # atomic scatter reorders sums: rounding-level differences of the working precision
+        tol = 1e-12 if prec == PF_F64 else 2e-6
+        S.set_graphs(False)
+        z_eager = host(S.vcycle(r, prec))
+        S.set_graphs(True)
+        for rep in range(4):
+            z = host(S.vcycle(r, prec))
+            e = rel_err(z, z_eager)
+            print(f"  prec {prec} replay {rep}: rel diff {e:.1e}", flush=True)
+            assert e <= tol
+            # eager work between replays
+            S.jacobian_apply(-1, r)
+            torch.cuda.synchronize()
+    # a new linearization invalidates the capture: the replay follows the new data
+    S.set_linearization(dev(U * 0.5), dev(phit), dev(act))
+    S.set_graphs(False)
+    z_eager2 = host(S.vcycle(r))
+    S.set_graphs(True)
+    assert rel_err(host(S.vcycle(r)), z_eager2) <= 1e-12
+
+
 @pytest.mark.parametrize("name,prec", [("cfg1_2d_q1_32", "f64"), ("cfg1_2d_q1_32", "f32"), ("small3d", "f64"),
                                        ("small3d_q2", "f32"), ("small_lshape", "f32")])
 def test_newton_step_matches_oracle(name, prec):
