@@ -1,0 +1,115 @@
+// Coarse-grid solve in one launch: the Chebyshev method used as the solver on
+// the coarsest level (Sec. 3.2.2) -- sweeps of r = b - G~ x, x += Cheb_B(r)
+// with the per-block interval [0.9 lam_min, 1.2 lam_max] -- run by a single
+// workgroup of Q1 cells.
+//
+// The coarsest level has a few hundred cells, so each operator apply is a
+// latency-bound sliver of work; issuing the ~40 applies and ~40 vector updates
+// of a coarse solve as separate kernels costs more in launch and drain time
+// than the arithmetic.  Here one workgroup loops over all steps.  The operand
+// and the result of each apply live in LDS (cell contributions are LDS
+// atomics, workgroup barriers order the steps, no device-scope fences); x and
+// r stay in global memory, each entry owned by one thread for the whole solve.
+// Q1 cells are split into a displacement and a phase-field work item.
+#include "q1_cell.h"
+
+namespace pff {
+
+constexpr int kCoarseThreads = 512;
+constexpr int kCoarseMaxDegree = 64;
+constexpr int64_t kCoarseMaxDofs = 4096;  // two LDS vectors of doubles: 64 KiB
+
+struct CoarseCoef {
+  int degree, sweeps;
+  double c1[2][kCoarseMaxDegree], c2[2][kCoarseMaxDegree];  // [block u/phi][step] of the three-term recurrence
+};
+
+// y = Pi_C x + sum over cells of the masked cell operator (full G~ if COUPLE, else B~); x, y in LDS
+template <int D, bool COUPLE>
+__device__ void wg_apply(const CellParams& cp, const double* x, double* y, const double* U, const double* phit,
+                         const uint8_t* mask) {
+  const int64_t nn = cp.n_nodes, n = (int64_t)(D + 1) * nn;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int c = (int)(i / nn);
+    y[i] = (mask[i - (int64_t)c * nn] & mask_bit(c, D)) ? x[i] : 0.0;
+  }
+  __syncthreads();
+  for (int64_t w = threadIdx.x; w < 2 * cp.n_cells; w += blockDim.x) {
+    const int64_t cid = w >> 1;
+    const int cx = (int)(cid % cp.N[0]);
+    const int cy = (int)((cid / cp.N[0]) % cp.N[1]);
+    const int cz = D == 3 ? (int)(cid / ((int64_t)cp.N[0] * cp.N[1])) : 0;
+    if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) continue;
+    const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
+    q1_cell_atomic<D, double, COUPLE>(cp, g0, x, U, phit, mask, y, 1 + (int)(w & 1));
+  }
+  __syncthreads();
+}
+
+template <int D>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, CoarseCoef cc, const double* U,
+                                                                 const double* phit, const uint8_t* mask,
+                                                                 const double* diag, const double* b, double* x,
+                                                                 double* r) {
+  extern __shared__ double lds[];
+  const int64_t nn = cp.n_nodes, n = (int64_t)(D + 1) * nn, nu = (int64_t)D * nn;
+  double* vd = lds;      // apply operand: the Chebyshev direction, or x at a sweep start
+  double* vt = lds + n;  // apply result
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
+  for (int sw = 0; sw < cc.sweeps; ++sw) {
+    if (sw == 0) {
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = b[i];
+    } else {
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) vd[i] = x[i];
+      __syncthreads();
+      wg_apply<D, true>(cp, vd, vt, U, phit, mask);
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = b[i] - vt[i];
+    }
+    for (int k = 0; k < cc.degree; ++k) {
+      if (k > 0) wg_apply<D, false>(cp, vd, vt, U, phit, mask);
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int blk = i >= nu ? 1 : 0;
+        const double c1 = cc.c1[blk][k], c2 = cc.c2[blk][k];
+        double ri = r[i], dn;
+        if (k == 0) {
+          dn = c2 * ri / diag[i];
+        } else {
+          ri -= vt[i];
+          r[i] = ri;
+          dn = c1 * vd[i] + c2 * ri / diag[i];
+        }
+        vd[i] = dn;
+        x[i] += dn;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Q1 levels up to kCoarseMaxDofs and degrees up to kCoarseMaxDegree; *handled = false otherwise
+pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
+                              const double* c2u, const double* c1p, const double* c2p, const double* U,
+                              const double* phit, const uint8_t* mask, const double* diag, const double* b,
+                              double* x, double* r, hipStream_t s, bool* handled) {
+  *handled = false;
+  if (g.p != 1 || degree > kCoarseMaxDegree || degree < 1 || g.n_dofs > kCoarseMaxDofs) return PF_OK;
+  CoarseCoef cc;
+  cc.degree = degree;
+  cc.sweeps = sweeps;
+  for (int k = 0; k < degree; ++k) {
+    cc.c1[0][k] = c1u[k];
+    cc.c2[0][k] = c2u[k];
+    cc.c1[1][k] = c1p[k];
+    cc.c2[1][k] = c2p[k];
+  }
+  const size_t lds = 2 * (size_t)g.n_dofs * sizeof(double);
+  if (g.d == 2)
+    k_coarse_solve<2><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  else
+    k_coarse_solve<3><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  PFF_CHECK_LAUNCH();
+  *handled = true;
+  return PF_OK;
+}
+
+}  // namespace pff

@@ -162,6 +162,25 @@ pf_status vec_jacobi(double* y, const double* x, const double* diag, const uint8
 pf_status vec_xpby_blocks(double* y, const double* x, const double beta[2], int64_t nn, int d, hipStream_t s);
 pf_status vec_axpy_blocks(double* y, const double* x, const double alpha[2], int64_t nn, int d, hipStream_t s);
 
+// Jacobi-PCG of the eigenvalue estimate with its scalars on the device: the
+// per-block coefficients alpha_k, beta_k accumulate in an EigDev record that
+// the host reads once after every level has run (no round trip per step).
+constexpr int kEigMaxSteps = 100;
+struct EigDev {
+  double rz[2], rz0[2], alpha[2], beta[2];
+  int done[2], n_al[2], n_be[2];
+  double al[2][kEigMaxSteps], be[2][kEigMaxSteps];
+};
+// z = p = D^-1 r (masked), then rz = rz0 = (r, z) per block
+pf_status eig_cg_begin(const double* r, double* z, double* p, const double* diag, const uint8_t* mask, int64_t nn,
+                       int d, double* d_partials, EigDev* st, hipStream_t s);
+// alpha_b = rz_b / (p, Ap)_b (a block with (p, Ap)_b <= 0 stops)
+pf_status eig_cg_alpha(const double* p, const double* Ap, int64_t nn, int d, double* d_partials, EigDev* st,
+                       hipStream_t s);
+// r -= alpha Ap, z = D^-1 r, beta_b = (r, z)_b / rz_b, p = z + beta p; a block stops once rz_b <= 1e-24 rz0_b
+pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const double* diag, const uint8_t* mask,
+                      int64_t nn, int d, double* d_partials, EigDev* st, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // structured grid kernels (grid.hip)
 // ---------------------------------------------------------------------------

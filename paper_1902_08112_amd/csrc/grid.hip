@@ -66,26 +66,64 @@ pf_status inject_mask(const Geom& gc, const Geom& gf, const uint8_t* fine, const
   return PF_OK;
 }
 
-template <typename Tin, typename Tout>
-__global__ void k_prolong(G3 c, G3 f, const Tin* in_c, Tout* out_f, const uint8_t* mask_f, int add) {
-  GRID_STRIDE(i, f.n_nodes) prolong_node<Tin, Tout>(c, f, i, in_c, out_f, mask_f, add);
+// one thread per (node, component), node fastest: neighbouring threads read
+// neighbouring lattice points of one component block
+template <int D, int P, typename Tin, typename Tout>
+__global__ void k_prolong(G3 c, G3 f, const Tin* __restrict__ in_c, Tout* __restrict__ out_f,
+                          const uint8_t* __restrict__ mask_f, int add) {
+  const int64_t n = (int64_t)(D + 1) * f.n_nodes;
+  GRID_STRIDE(t, n) {
+    const int comp = (int)(t / f.n_nodes);
+    const int64_t i = t - (int64_t)comp * f.n_nodes;
+    const bool con = mask_f && (mask_f[i] & mask_bit(comp, D));
+    if (add) {
+      if (!con) out_f[t] = (Tout)((double)out_f[t] + prolong_dof<D, P, Tin>(c, f, i, comp, in_c));
+    } else {
+      out_f[t] = (Tout)(con ? 0.0 : prolong_dof<D, P, Tin>(c, f, i, comp, in_c));
+    }
+  }
 }
-template <typename Tin, typename Tout>
-__global__ void k_restrict(G3 c, G3 f, const Tin* in_f, Tout* out_c, const uint8_t* mask_c) {
-  GRID_STRIDE(j, c.n_nodes) restrict_node<Tin, Tout>(c, f, j, in_f, out_c, mask_c);
+template <int D, int P, typename Tin, typename Tout>
+__global__ void k_restrict(G3 c, G3 f, const Tin* __restrict__ in_f, Tout* __restrict__ out_c,
+                           const uint8_t* __restrict__ mask_c) {
+  const int64_t n = (int64_t)(D + 1) * c.n_nodes;
+  GRID_STRIDE(t, n) {
+    const int comp = (int)(t / c.n_nodes);
+    const int64_t j = t - (int64_t)comp * c.n_nodes;
+    const bool con = mask_c && (mask_c[j] & mask_bit(comp, D));
+    out_c[t] = (Tout)(con ? 0.0 : restrict_dof<D, P, Tin>(c, f, j, comp, in_f));
+  }
 }
 
 template <typename Tin, typename Tout>
 pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, Tout* out_c, const uint8_t* mask_c,
                        hipStream_t s) {
-  k_restrict<Tin, Tout><<<nblk(gc.n_nodes), 256, 0, s>>>(g3(gc), g3(gf), in_f, out_c, mask_c);
+  const int64_t n = gc.n_dofs;
+  const G3 c = g3(gc), f = g3(gf);
+  if (gf.d == 2 && gf.p == 1)
+    k_restrict<2, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+  else if (gf.d == 2)
+    k_restrict<2, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+  else if (gf.p == 1)
+    k_restrict<3, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+  else
+    k_restrict<3, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
 template <typename Tin, typename Tout>
 pf_status prolong_vec(const Geom& gc, const Geom& gf, const Tin* in_c, Tout* out_f, const uint8_t* mask_f, int add,
                       hipStream_t s) {
-  k_prolong<Tin, Tout><<<nblk(gf.n_nodes), 256, 0, s>>>(g3(gc), g3(gf), in_c, out_f, mask_f, add);
+  const int64_t n = gf.n_dofs;
+  const G3 c = g3(gc), f = g3(gf);
+  if (gf.d == 2 && gf.p == 1)
+    k_prolong<2, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_c, out_f, mask_f, add);
+  else if (gf.d == 2)
+    k_prolong<2, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_c, out_f, mask_f, add);
+  else if (gf.p == 1)
+    k_prolong<3, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_c, out_f, mask_f, add);
+  else
+    k_prolong<3, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_c, out_f, mask_f, add);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }

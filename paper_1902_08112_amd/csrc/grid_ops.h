@@ -207,6 +207,99 @@ __device__ inline void restrict_node(const G3& c, const G3& f, int64_t j, const 
   }
 }
 
+// Fixed-shape forms of the two transfers for one (node, component): the 1D
+// stencils are unrolled per axis (3 fine nodes per coarse node and axis for
+// Q1, 7 for Q2 in restriction; 2 resp. 3 coarse nodes in prolongation) and
+// out-of-lattice taps get weight 0 at a clamped, in-bounds address.
+template <int P>
+__device__ inline void restrict_taps(int ic, int nnf, int Nc, int64_t stride, double w[4 * P - 1],
+                                     int64_t off[4 * P - 1]) {
+#pragma unroll
+  for (int t = 0; t < 4 * P - 1; ++t) {
+    const int fi = 2 * ic + t - (2 * P - 1);
+    const bool in = fi >= 0 && fi < nnf;
+    w[t] = in ? w1d(P, fi, ic, Nc) : 0.0;
+    off[t] = in ? (int64_t)fi * stride : 0;
+  }
+}
+template <int P>
+__device__ inline void prolong_taps(int fi, int Nc, int64_t stride, double w[P + 1], int64_t off[P + 1]) {
+  if constexpr (P == 1) {
+    const int j0 = fi >> 1;
+    const bool odd = fi & 1;
+    w[0] = odd ? 0.5 : 1.0;
+    off[0] = (int64_t)j0 * stride;
+    w[1] = odd ? 0.5 : 0.0;
+    off[1] = (int64_t)(odd ? j0 + 1 : j0) * stride;
+  } else {
+    int cc = fi / 4;
+    if (cc > Nc - 1) cc = Nc - 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      w[a] = w1d(2, fi, 2 * cc + a, Nc);
+      off[a] = (int64_t)(2 * cc + a) * stride;
+    }
+  }
+}
+
+// (P^T in_f) at coarse node j, component comp
+template <int D, int P, typename Tin>
+__device__ inline double restrict_dof(const G3& c, const G3& f, int64_t j, int comp, const Tin* __restrict__ in_f) {
+  constexpr int T = 4 * P - 1;
+  int idx[3];
+  node_idx(c, j, idx);
+  double wx[T], wy[T], wz[T];
+  int64_t ox[T], oy[T], oz[T];
+  restrict_taps<P>(idx[0], f.nn[0], c.N[0], f.ns[0], wx, ox);
+  restrict_taps<P>(idx[1], f.nn[1], c.N[1], f.ns[1], wy, oy);
+  if constexpr (D == 3) restrict_taps<P>(idx[2], f.nn[2], c.N[2], f.ns[2], wz, oz);
+  const Tin* src = in_f + (int64_t)comp * f.n_nodes;
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const double wab = wx[a] * wy[b];
+      if constexpr (D == 3) {
+#pragma unroll
+        for (int e = 0; e < T; ++e)
+          if (wab * wz[e] != 0.0) acc += wab * wz[e] * (double)src[ox[a] + oy[b] + oz[e]];
+      } else {
+        if (wab != 0.0) acc += wab * (double)src[ox[a] + oy[b]];
+      }
+    }
+  return acc;
+}
+
+// (P in_c) at fine node i, component comp
+template <int D, int P, typename Tin>
+__device__ inline double prolong_dof(const G3& c, const G3& f, int64_t i, int comp, const Tin* __restrict__ in_c) {
+  constexpr int T = P + 1;
+  int idx[3];
+  node_idx(f, i, idx);
+  double wx[T], wy[T], wz[T];
+  int64_t ox[T], oy[T], oz[T];
+  prolong_taps<P>(idx[0], c.N[0], c.ns[0], wx, ox);
+  prolong_taps<P>(idx[1], c.N[1], c.ns[1], wy, oy);
+  if constexpr (D == 3) prolong_taps<P>(idx[2], c.N[2], c.ns[2], wz, oz);
+  const Tin* src = in_c + (int64_t)comp * c.n_nodes;
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const double wab = wx[a] * wy[b];
+      if constexpr (D == 3) {
+#pragma unroll
+        for (int e = 0; e < T; ++e)
+          if (wab * wz[e] != 0.0) acc += wab * wz[e] * (double)src[ox[a] + oy[b] + oz[e]];
+      } else {
+        if (wab != 0.0) acc += wab * (double)src[ox[a] + oy[b]];
+      }
+    }
+  return acc;
+}
+
 // lumped mass: sum over adjacent active cells of the product of 1D Gauss-Lobatto weights times h
 __device__ inline double lumped_node(const G3& g, int64_t i) {
   int idx[3];

@@ -219,10 +219,12 @@ __device__ __forceinline__ void cell2_phi(const Consts<T>& k, const T du[2][4], 
 // One Q1 cell (corner node g0 of a lattice with strides sy, sz): masked
 // Jacobian (COUPLE) or block apply, contributions added atomically to y on
 // the free DoFs.  x, U, phit, mask, y are the instance's own arrays.
+// part: 0 = both parts, 1 = displacement rows only, 2 = phase-field rows only
 template <int D, typename T, bool COUPLE>
 __device__ __forceinline__ void q1_cell_atomic(const CellParams& cp, int64_t g0, const T* __restrict__ x,
                                                const T* __restrict__ U, const T* __restrict__ phit,
-                                               const uint8_t* __restrict__ mask, T* __restrict__ y) {
+                                               const uint8_t* __restrict__ mask, T* __restrict__ y,
+                                               int part = 0) {
   constexpr int NL = D == 2 ? 4 : 8;
   const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
   int64_t gi[NL];
@@ -241,7 +243,7 @@ __device__ __forceinline__ void q1_cell_atomic(const CellParams& cp, int64_t g0,
       du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
     }
   }
-  {
+  if (part != 2) {
     T outu[D][NL];
     if constexpr (D == 3)
       cell3_u<T>(kc, du, pt, outu);
@@ -253,6 +255,7 @@ __device__ __forceinline__ void q1_cell_atomic(const CellParams& cp, int64_t g0,
       for (int a = 0; a < NL; ++a)
         if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
   }
+  if (part == 1) return;
   T dp[NL], uu[D][NL], ph[NL], outp[NL];
 #pragma unroll
   for (int a = 0; a < NL; ++a) {

@@ -23,6 +23,10 @@ pf_status launch_cell_q1_d(const Geom&, const CellParams&, int, const double*, c
                            const uint8_t*, double*, hipStream_t, bool* handled);
 pf_status launch_cell_q1_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
                            const uint8_t*, float*, hipStream_t, bool* handled);
+pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
+                              const double* c2u, const double* c1p, const double* c2p, const double* U,
+                              const double* phit, const uint8_t* mask, const double* diag, const double* b,
+                              double* x, double* r, hipStream_t s, bool* handled);
 
 template <>
 pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
@@ -138,6 +142,7 @@ struct pf_ctx {
   uint8_t *extra = nullptr, *active = nullptr;
   double *V = nullptr, *Z = nullptr;
   double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
+  EigDev* eigdev = nullptr;  // one record per level
   // captured V-cycles per precision (input vin, output vout); invalid after any change of
   // level data, eigenvalue bounds or kernel tuning
   double *vin = nullptr, *vout = nullptr;
@@ -146,6 +151,7 @@ struct pf_ctx {
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
   bool use_graphs = true;
+  bool fused_coarse = true;  // coarse Chebyshev solve in one single-workgroup launch
   void drop_graphs() {
     for (int k = 0; k < 2; ++k) {
       if (vexec[k]) hipGraphExecDestroy(vexec[k]);
@@ -326,6 +332,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
   double* part_md = cv.take<double>((size_t)256 * (mr + 2));
   double* dscal = cv.take<double>(1024);
+  EigDev* eigdev = cv.take<EigDev>(L);
   double* vin = cv.take<double>(nd);
   double* vout = cv.take<double>(nd);
   if (c) {
@@ -343,6 +350,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->part = part;
     c->part_md = part_md;
     c->dscal = dscal;
+    c->eigdev = eigdev;
     c->vin = vin;
     c->vout = vout;
   }
@@ -433,6 +441,13 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
   const pf_options& o = c->opt;
   const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
   const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
+  if (c->fused_coarse) {
+    const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
+    bool handled = false;
+    PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
+                                cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, bb, x, r, s, &handled));
+    if (handled) return PF_OK;
+  }
   PFF_TRY(vec_fill<double>(x, 0.0, b.g.n_dofs, s));
   for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
     if (sw == 0) {
@@ -542,69 +557,63 @@ pf_status vcycle_any(pf_ctx* c, int vprec, const double* r, double* z, hipStream
 // ---------------------------------------------------------------------------
 // eigenvalue estimates: PCG on D^{-1} B~_bb per block (both blocks in one apply)
 // ---------------------------------------------------------------------------
-pf_status estimate_eigs(pf_ctx* c, int l, hipStream_t s) {
+// Launch the Jacobi-PCG of level l (both diagonal blocks, lockstep); the
+// coefficients stay in c->eigdev[l] until eig_from_cg reads them.
+pf_status launch_eig_cg(pf_ctx* c, int l, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   const Geom& g = b.g;
   double* r = (double*)b.vr;
   double* z = (double*)b.vd;
   double* p = (double*)b.vb;
   double* Ap = (double*)b.vt;
+  EigDev* st = c->eigdev + l;
   const uint64_t seed = c->opt.eig_seed;
   const uint64_t su = seed + (uint64_t)l * 0x1000003ull + 0ull * 0x10001ull;
   const uint64_t sp = seed + (uint64_t)l * 0x1000003ull + 1ull * 0x10001ull;
   PFF_TRY(eig_start_vector(r, b.mask, g.n_nodes, g.d, su, sp, s));
-  PFF_TRY(vec_jacobi(z, r, b.diag, b.mask, g.n_nodes, g.d, s));
-  PFF_TRY(vec_copy<double>(p, z, g.n_dofs, s));
-  double rz[2], rz0[2], pAp[2], rzn[2];
-  PFF_TRY(dot_blocks(r, z, g.n_nodes, g.d, c->part, rz, s));
-  rz0[0] = rz[0];
-  rz0[1] = rz[1];
-  bool done[2] = {!(rz0[0] > 0), !(rz0[1] > 0)};
-  std::vector<double> al[2], be[2];
+  PFF_TRY(eig_cg_begin(r, z, p, b.diag, b.mask, g.n_nodes, g.d, c->part, st, s));
   for (int it = 0; it < c->opt.eig_cg_steps; ++it) {
-    for (int k = 0; k < 2; ++k)
-      if (!done[k] && (rz[k] <= 0.0 || rz[k] <= 1e-24 * rz0[k])) done[k] = true;
-    if (done[0] && done[1]) break;
     PFF_TRY(level_apply(c, l, PF_F64, MODE_BLOCK, p, Ap, s));
-    PFF_TRY(dot_blocks(p, Ap, g.n_nodes, g.d, c->part, pAp, s));
-    double alpha[2] = {0, 0};
-    for (int k = 0; k < 2; ++k) {
-      if (done[k]) continue;
-      if (!(pAp[k] > 0.0)) {
-        done[k] = true;
-        continue;
-      }
-      alpha[k] = rz[k] / pAp[k];
-      al[k].push_back(alpha[k]);
-    }
-    const double nal[2] = {-alpha[0], -alpha[1]};
-    PFF_TRY(vec_axpy_blocks(r, Ap, nal, g.n_nodes, g.d, s));
-    PFF_TRY(vec_jacobi(z, r, b.diag, b.mask, g.n_nodes, g.d, s));
-    PFF_TRY(dot_blocks(r, z, g.n_nodes, g.d, c->part, rzn, s));
-    double beta[2] = {0, 0};
-    for (int k = 0; k < 2; ++k) {
-      if (done[k]) continue;
-      beta[k] = rzn[k] / rz[k];
-      be[k].push_back(beta[k]);
-      rz[k] = rzn[k];
-    }
-    PFF_TRY(vec_xpby_blocks(p, z, beta, g.n_nodes, g.d, s));
+    PFF_TRY(eig_cg_alpha(p, Ap, g.n_nodes, g.d, c->part, st, s));
+    PFF_TRY(eig_cg_beta(r, Ap, z, p, b.diag, b.mask, g.n_nodes, g.d, c->part, st, s));
   }
+  return PF_OK;
+}
+
+// Lanczos tridiagonal of the CG coefficients -> extreme eigenvalues per block
+void eig_from_cg(const EigDev& e, double eig[4]) {
   for (int k = 0; k < 2; ++k) {
-    const size_t n = al[k].size();
+    const int n = e.n_al[k];
     if (n == 0) {
-      b.eig[2 * k] = 1.0;
-      b.eig[2 * k + 1] = 1.0;
+      eig[2 * k] = 1.0;
+      eig[2 * k + 1] = 1.0;
       continue;
     }
     std::vector<double> a(n), off(n > 1 ? n - 1 : 0);
-    for (size_t j = 0; j < n; ++j) {
-      a[j] = 1.0 / al[k][j] + (j ? be[k][j - 1] / al[k][j - 1] : 0.0);
-      if (j + 1 < n) off[j] = std::sqrt(be[k][j]) / al[k][j];
+    for (int j = 0; j < n; ++j) {
+      a[j] = 1.0 / e.al[k][j] + (j ? e.be[k][j - 1] / e.al[k][j - 1] : 0.0);
+      if (j + 1 < n) off[j] = std::sqrt(e.be[k][j]) / e.al[k][j];
     }
-    b.eig[2 * k] = tridiag_eig(a, off, 0);
-    b.eig[2 * k + 1] = tridiag_eig(a, off, (int)n - 1);
+    eig[2 * k] = tridiag_eig(a, off, 0);
+    eig[2 * k + 1] = tridiag_eig(a, off, n - 1);
   }
+}
+
+// every level without fixed bounds: launch all CG runs, then one read-back
+pf_status estimate_eigs_all(pf_ctx* c, hipStream_t s) {
+  const int L = (int)c->lev.size();
+  bool any = false;
+  for (int l = 0; l < L; ++l)
+    if (!c->lev[l].eig_fixed) {
+      PFF_TRY(launch_eig_cg(c, l, s));
+      any = true;
+    }
+  if (!any) return PF_OK;
+  std::vector<EigDev> h(L);
+  PFF_HIP(hipMemcpyAsync(h.data(), c->eigdev, sizeof(EigDev) * L, hipMemcpyDeviceToHost, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  for (int l = 0; l < L; ++l)
+    if (!c->lev[l].eig_fixed) eig_from_cg(h[l], c->lev[l].eig);
   return PF_OK;
 }
 
@@ -628,8 +637,7 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
     PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
     PFF_TRY(vec_cast<double, float>(b.diag32, b.diag, b.g.n_dofs, s));
   }
-  for (int l = 0; l <= L; ++l)
-    if (!c->lev[l].eig_fixed) PFF_TRY(estimate_eigs(c, l, s));
+  PFF_TRY(estimate_eigs_all(c, s));
   PFF_HIP(hipStreamSynchronize(s));
   c->has_lin = true;
   c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle

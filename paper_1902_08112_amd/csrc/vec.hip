@@ -349,8 +349,119 @@ pf_status vec_axpy_blocks(double* y, const double* x, const double alpha[2], int
   return PF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// device-resident Jacobi-PCG for the eigenvalue estimate.  The reductions use
+// the same grid, loop order and final block as dot_blocks, so the
+// coefficients equal those of a host-driven loop bit for bit.
+// ---------------------------------------------------------------------------
+// z = D^-1 (r - alpha q) on free DoFs (r updated when q != nullptr), p = z if
+// p != nullptr; partials of (r, z) per block
+__global__ void k_eig_precond(double* r, const double* q, const EigDev* st, double* z, double* p, const double* diag,
+                              const uint8_t* mask, int64_t nn, int d, double* partials) {
+  const int64_t nu = (int64_t)d * nn, n = nu + nn;
+  for (int k = 0; k < 2; ++k) {
+    const int64_t lo = k == 0 ? 0 : nu, hi = k == 0 ? nu : n;
+    const double na = q ? -st->alpha[k] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      double ri = r[i];
+      if (q) {
+        ri += na * q[i];
+        r[i] = ri;
+      }
+      const int c = (int)(i / nn);
+      const double zi = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? 0.0 : ri / diag[i];
+      z[i] = zi;
+      if (p) p[i] = zi;
+      acc += ri * zi;
+    }
+    const double b = block_sum(acc);
+    if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+// phase 0: start; 1: alpha from (p, Ap); 2: beta from the new (r, z)
+__global__ void k_eig_update(const double* partials, int nparts, EigDev* st, int phase) {
+  double tot[2];
+  for (int k = 0; k < 2; ++k) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partials[k * nparts + i];
+    tot[k] = block_sum(acc);
+  }
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 2; ++k) {
+    if (phase == 0) {
+      st->rz[k] = st->rz0[k] = tot[k];
+      st->done[k] = !(tot[k] > 0.0);
+      st->n_al[k] = st->n_be[k] = 0;
+      st->alpha[k] = st->beta[k] = 0.0;
+    } else if (phase == 1) {
+      double a = 0.0;
+      if (!st->done[k]) {
+        if (!(tot[k] > 0.0)) {
+          st->done[k] = 1;
+        } else {
+          a = st->rz[k] / tot[k];
+          st->al[k][st->n_al[k]++] = a;
+        }
+      }
+      st->alpha[k] = a;
+    } else {
+      double b = 0.0;
+      if (!st->done[k]) {
+        b = tot[k] / st->rz[k];
+        st->be[k][st->n_be[k]++] = b;
+        st->rz[k] = tot[k];
+        if (st->rz[k] <= 0.0 || st->rz[k] <= 1e-24 * st->rz0[k]) st->done[k] = 1;
+      }
+      st->beta[k] = b;
+    }
+  }
+}
+
+__global__ void k_eig_xpby(double* p, const double* z, const EigDev* st, int64_t nu, int64_t n) {
+  const double bu = st->beta[0], bp = st->beta[1];
+  GRID_STRIDE(i, n) p[i] = z[i] + (i >= nu ? bp : bu) * p[i];
+}
+
+pf_status eig_cg_begin(const double* r, double* z, double* p, const double* diag, const uint8_t* mask, int64_t nn,
+                       int d, double* d_part, EigDev* st, hipStream_t s) {
+  const int64_t n = (int64_t)(d + 1) * nn;
+  const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
+  k_eig_precond<<<nb, kRedBlock, 0, s>>>(const_cast<double*>(r), nullptr, st, z, p, diag, mask, nn, d, d_part);
+  PFF_CHECK_LAUNCH();
+  k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 0);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+pf_status eig_cg_alpha(const double* p, const double* Ap, int64_t nn, int d, double* d_part, EigDev* st,
+                       hipStream_t s) {
+  const int64_t n = (int64_t)(d + 1) * nn;
+  const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
+  k_dot_segments<<<nb, kRedBlock, 0, s>>>(p, Ap, 0, (int64_t)d * nn, n, 2, d_part);
+  PFF_CHECK_LAUNCH();
+  k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 1);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const double* diag, const uint8_t* mask,
+                      int64_t nn, int d, double* d_part, EigDev* st, hipStream_t s) {
+  const int64_t n = (int64_t)(d + 1) * nn;
+  const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
+  k_eig_precond<<<nb, kRedBlock, 0, s>>>(r, Ap, st, z, nullptr, diag, mask, nn, d, d_part);
+  PFF_CHECK_LAUNCH();
+  k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 2);
+  PFF_CHECK_LAUNCH();
+  k_eig_xpby<<<nblocks(n), 256, 0, s>>>(p, z, st, (int64_t)d * nn, n);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
 // explicit instantiations
-#define INST_T(T)                                                                                              \
+#define INST_T(T)                                                                                             \
   template pf_status vec_fill<T>(T*, T, int64_t, hipStream_t);                                                 \
   template pf_status vec_copy<T>(T*, const T*, int64_t, hipStream_t);                                          \
   template pf_status vec_init_constrained<T>(T*, const T*, const uint8_t*, int64_t, int, hipStream_t);         \
