@@ -223,9 +223,12 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
  * every level, precision and operator (mode 0: G~, mode 1: smoother block
  * B~) it times `reps` applies of each candidate kernel shape with HIP events
  * on `stream` and keeps the fastest in the context.  Candidates: variant 2 =
- * one thread per cell with atomic scatter; variant 0 / 1 = one wavefront per
- * 8x8 / 16x4 tile of cells marching through chunks of zc node planes with
- * register carries (owner-computes, deterministic).  Requires
+ * one thread per cell with atomic scatter; variant 4 = two threads per cell
+ * (displacement / phase-field rows) with atomic scatter; variant 3 (3D) =
+ * 256-thread bricks of cells staged through LDS with atomic scatter;
+ * variant 0 / 1 = one wavefront per 8x8 / 16x4 tile of cells marching
+ * through chunks of zc node planes with register carries (owner-computes,
+ * deterministic).  Requires
  * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
  * Q2 levels have one kernel and are skipped. */
 pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);

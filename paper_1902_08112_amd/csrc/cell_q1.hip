@@ -303,8 +303,114 @@ __global__ __launch_bounds__(128) void k_q1_2d_atomic(CellParams cp, const T* __
     if (!(mk[a] & kMaskPhi)) atomicAdd(&y[2 * nn + gi[a]], outp[a]);
 }
 
+// ----------------------------------------------------------------------------------- 3D bricks
+// One 256-thread workgroup per brick of kBX x kBY x kBZ cells.  The brick's
+// (kBX+1)(kBY+1)(kBZ+1) nodes of x, U, phi~ and the mask are first copied to
+// LDS with row-contiguous loads (each node value read from HBM once per
+// brick instead of once per adjacent cell), then every thread evaluates one
+// cell from LDS and scatters with atomics as the atomic variant does.  The
+// FP64 cell needs ~250 VGPRs (two waves per SIMD); two co-resident bricks per
+// CU overlap one brick's staging with the other's arithmetic.
+constexpr int kBX = 16, kBY = 4, kBZ = 4;
+constexpr int kBNX = kBX + 1, kBNY = kBY + 1, kBNZ = kBZ + 1, kBN = kBNX * kBNY * kBNZ;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_q1_3d_brick(CellParams cp, const T* __restrict__ x,
+                                                     const T* __restrict__ U, const T* __restrict__ phit,
+                                                     const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  constexpr int NU = COUPLE ? 4 : 3;  // U components the cell reads
+  __shared__ T sx[4][kBN];
+  __shared__ T sU[NU][kBN];
+  __shared__ T sp[kBN];
+  __shared__ uint8_t sm[kBN];
+  const int nbx = (cp.N[0] + kBX - 1) / kBX, nby = (cp.N[1] + kBY - 1) / kBY;
+  const int bx = (int)(blockIdx.x % nbx), by = (int)((blockIdx.x / nbx) % nby), bz = (int)(blockIdx.x / (nbx * nby));
+  const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  for (int t = threadIdx.x; t < kBN; t += blockDim.x) {
+    const int ix = t % kBNX, iy = (t / kBNX) % kBNY, iz = t / (kBNX * kBNY);
+    const int gx = x0 + ix, gy = y0 + iy, gz = z0 + iz;
+    const bool in = gx < cp.nn[0] && gy < cp.nn[1] && gz < cp.nn[2];
+    const int64_t g = in ? (int64_t)gx + (int64_t)gy * sy + (int64_t)gz * sz : 0;
+    sm[t] = in ? mask[g] : (uint8_t)0xFF;
+    sp[t] = in ? phit[g] : T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sx[c][t] = in ? x[c * nn + g] : T(0);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) sU[c][t] = in ? U[c * nn + g] : T(0);
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % kBX, ly = (threadIdx.x / kBX) % kBY, lz = threadIdx.x / (kBX * kBY);
+  const int cx = x0 + lx, cy = y0 + ly, cz = z0 + lz;
+  if (cx >= cp.N[0] || cy >= cp.N[1] || cz >= cp.N[2] || cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
+  const int64_t g0 = (int64_t)cx + (int64_t)cy * sy + (int64_t)cz * sz;
+  const int l0 = lx + ly * kBNX + lz * kBNX * kBNY;
+  int li[8];
+  int64_t gi[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    li[a] = l0 + (a & 1) + ((a >> 1) & 1) * kBNX + (a >> 2) * kBNX * kBNY;
+    gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (a >> 2) * sz;
+  }
+  const Consts<T> kc(cp, 8);
+  uint8_t mk[8];
+  T du[3][8];
+  {
+    T pt[8], outu[3][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      mk[a] = sm[li[a]];
+      pt[a] = sp[li[a]];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) du[c][a] = (mk[a] & (1 << c)) ? T(0) : sx[c][li[a]];
+    }
+    cell3_u<T>(kc, du, pt, outu);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
+  }
+  T dp[8], uu[3][8], ph[8], outp[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    dp[a] = (mk[a] & kMaskPhi) ? T(0) : sx[3][li[a]];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) uu[c][a] = sU[c][li[a]];
+    ph[a] = COUPLE ? sU[NU - 1][li[a]] : T(0);
+  }
+  cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    if (!(mk[a] & kMaskPhi)) atomicAdd(&y[3 * nn + gi[a]], outp[a]);
+}
+
+// ----------------------------------------------------------------------------------- split cells
+// Two work items per cell: the displacement rows and the phase-field rows are
+// evaluated by different wavefronts (each wave is uniform in its part, so
+// there is no divergence), halving the serial chain per lane.  For levels
+// too small to fill the chip, where a cell's latency is the cost.
+template <int D, typename T, int MODE>
+__global__ __launch_bounds__(128) void k_q1_split(CellParams cp, const T* __restrict__ x, const T* __restrict__ U,
+                                                  const T* __restrict__ phit, const uint8_t* __restrict__ mask,
+                                                  T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int part = 1 + (int)((w >> 6) & 1);
+  const int64_t cid = (w >> 7) * 64 + (w & 63);
+  if (cid >= cp.n_cells) return;
+  const int cx = (int)(cid % cp.N[0]);
+  const int cy = (int)((cid / cp.N[0]) % cp.N[1]);
+  const int cz = D == 3 ? (int)(cid / ((int64_t)cp.N[0] * cp.N[1])) : 0;
+  if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
+  const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
+  q1_cell_atomic<D, T, COUPLE>(cp, g0, x, U, phit, mask, y, part);
+}
+
 // ----------------------------------------------------------------------------------- dispatch
-// Variant per level: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles, 2 = atomic.
+// Variant per level: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles, 2 = atomic,
+// 3 = LDS-staged bricks (3D; 2D maps it to 2), 4 = split cells (two work items per cell).
 // q1_set_tile forces a variant / z-chunk (tuning and tests); -1 restores the heuristic.
 static int64_t q1_tiles_xy(const Geom& g, int tile) {
   if (g.d == 2) return (g.nn[0] + 62) / 63;
@@ -326,7 +432,11 @@ int q1_chunk(const Geom& g, int variant, int requested_zc) {
 // where they fill the chip with chunks of >= 8 planes.
 int q1_variant(const Geom& g, int mode, int requested) {
   if (!(g.p == 1 && (mode == MODE_APPLY || mode == MODE_BLOCK) && (g.d == 2 || g.d == 3))) return -1;
-  if (requested >= 0 && requested < kQ1Variants) return (g.d == 2 && requested == 1) ? 0 : requested;
+  if (requested >= 0 && requested < kQ1Variants) {
+    if (g.d == 2 && requested == 1) return 0;
+    if (g.d == 2 && requested == 3) return 2;
+    return requested;
+  }
   const int nplanes = g.nn[g.d - 1];
   return q1_tiles_xy(g, 0) * ((nplanes + 7) / 8) >= 4096 ? 0 : 2;
 }
@@ -340,6 +450,31 @@ template <typename T>
 static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                            const uint8_t* mask, T* y, hipStream_t s) {
   const int variant = q1_variant(g, mode, cp.variant);
+  if (variant == 4) {
+    const int64_t nb = (2 * ((g.n_cells + 63) / 64) * 64 + 127) / 128;
+    if (g.d == 3) {
+      if (mode == MODE_APPLY)
+        k_q1_split<3, T, MODE_APPLY><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+      else
+        k_q1_split<3, T, MODE_BLOCK><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+    } else {
+      if (mode == MODE_APPLY)
+        k_q1_split<2, T, MODE_APPLY><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+      else
+        k_q1_split<2, T, MODE_BLOCK><<<nb, 128, 0, s>>>(cp, x, U, phit, mask, y);
+    }
+    PFF_CHECK_LAUNCH();
+    return PF_OK;
+  }
+  if (variant == 3) {
+    const int64_t nb = (int64_t)((g.N[0] + kBX - 1) / kBX) * ((g.N[1] + kBY - 1) / kBY) * ((g.N[2] + kBZ - 1) / kBZ);
+    if (mode == MODE_APPLY)
+      k_q1_3d_brick<T, MODE_APPLY><<<nb, 256, 0, s>>>(cp, x, U, phit, mask, y);
+    else
+      k_q1_3d_brick<T, MODE_BLOCK><<<nb, 256, 0, s>>>(cp, x, U, phit, mask, y);
+    PFF_CHECK_LAUNCH();
+    return PF_OK;
+  }
   if (variant == 2) {
     const int64_t nb = (g.n_cells + 127) / 128;
     if (g.d == 3) {

@@ -101,8 +101,10 @@ pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x,
                       const uint8_t* mask, T* y, hipStream_t s);
 
 // Q1 cell-loop variants: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles (both
-// write every node of y themselves), 2 = one thread per cell with atomics (y pre-set).
-constexpr int kQ1Variants = 3;
+// write every node of y themselves), 2 = one thread per cell with atomics (y pre-set),
+// 3 = LDS-staged bricks of cells with atomics (3D, y pre-set), 4 = two work items
+// (displacement / phase-field rows) per cell with atomics (y pre-set).
+constexpr int kQ1Variants = 5;
 int q1_variant(const Geom& g, int mode, int requested);
 bool q1_tiled_handles(const Geom& g, int mode, int requested);
 // marching chunk the tiled kernels use for this level and request
@@ -132,9 +134,10 @@ pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s);
 // Chebyshev step (per block coefficients c1[2], c2[2]; blocks u / phi):
 //   first:  d = c2 * Dinv * res;           x += d
 //   other:  res -= t; d = c1*d + c2*Dinv*res; x += d
+// t_next (may alias t, or nullptr): t_next = Pi_C d, the starting value of the next apply
 template <typename T>
 pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int first, int64_t nn, int d, hipStream_t s);
+                        int first, int64_t nn, int d, const uint8_t* mask, T* t_next, hipStream_t s);
 // dots per block: out[0] = sum over u-block of x*y, out[1] over the phi-block (FP64 accumulation)
 pf_status dot_blocks(const double* x, const double* y, int64_t nn, int d, double* d_partials, double* h_out,
                      hipStream_t s);

@@ -51,11 +51,12 @@ static bool starts_from_constrained(int mode) { return mode == MODE_APPLY || mod
 // overwrite y with the operator result on one level's data
 template <typename T>
 pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
-                   const uint8_t* mask, T* y, hipStream_t s) {
+                   const uint8_t* mask, T* y, hipStream_t s, bool y_preset = false) {
   if (q1_tiled_handles(g, mode, cp.variant)) {
     // the tiled kernels write every entry, identity rows included
   } else if (starts_from_constrained(mode)) {
-    PFF_TRY(vec_init_constrained<T>(y, x, mask, g.n_nodes, g.d, s));
+    // y = Pi_C x, unless the producer of x already wrote it
+    if (!y_preset) PFF_TRY(vec_init_constrained<T>(y, x, mask, g.n_nodes, g.d, s));
   } else {
     PFF_TRY(vec_fill<T>(y, T(0), g.n_dofs, s));
   }
@@ -130,7 +131,7 @@ struct LevelBuf {
   // cell-loop choice per [precision][mode APPLY/BLOCK]: variant and marching chunk (-1: heuristic)
   int variant[2][2] = {{-1, -1}, {-1, -1}};
   int zc[2][2] = {{-1, -1}, {-1, -1}};
-  double tune_us[2][2][8] = {};  // measured candidates (autotune report)
+  double tune_us[2][2][12] = {};  // measured candidates (autotune report)
 };
 
 struct pf_ctx {
@@ -364,7 +365,7 @@ int level_prec(pf_ctx* c, int l, int vprec) { return l == 0 ? PF_F64 : vprec; }
 // ---------------------------------------------------------------------------
 // operator on level l in precision prec (x, y point to that precision)
 // ---------------------------------------------------------------------------
-pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s) {
+CellParams level_params(pf_ctx* c, int l, int prec, int mode) {
   LevelBuf& b = c->lev[l];
   CellParams cp = cparams(c, l);
   if (mode == MODE_APPLY || mode == MODE_BLOCK) {
@@ -372,9 +373,23 @@ pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void*
     cp.variant = b.variant[pi][mi];
     cp.zc = b.zc[pi][mi];
   }
+  return cp;
+}
+
+// whether the (level, prec, mode) operator starts from y = Pi_C x written by a separate pass
+bool apply_needs_preset(pf_ctx* c, int l, int prec, int mode) {
+  const CellParams cp = level_params(c, l, prec, mode);
+  return !q1_tiled_handles(c->lev[l].g, mode, cp.variant);
+}
+
+// y_preset: the caller already stored y = Pi_C x (fused into the kernel that produced x)
+pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s,
+                      bool y_preset = false) {
+  LevelBuf& b = c->lev[l];
+  const CellParams cp = level_params(c, l, prec, mode);
   if (prec == PF_F64)
-    return apply_op<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s);
-  return apply_op<float>(b.g, cp, mode, (const float*)x, b.U32, b.phit32, b.mask, (float*)y, s);
+    return apply_op<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s, y_preset);
+  return apply_op<float>(b.g, cp, mode, (const float*)x, b.U32, b.phit32, b.mask, (float*)y, s, y_preset);
 }
 
 // Chebyshev coefficients of step k for one block: interval [lo, hi]
@@ -406,10 +421,13 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
   T* dv = (T*)b.vd;
   T* t = (T*)b.vt;
   const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
+  // the step that produces the next direction also writes t = Pi_C dv for the next apply
+  const bool fuse = apply_needs_preset(c, l, prec, MODE_BLOCK);
   for (int k = 0; k < degree; ++k) {
-    if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s));
+    if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s, fuse));
     const double c1[2] = {cu.c1[k], cpz.c1[k]}, c2[2] = {cu.c2[k], cpz.c2[k]};
-    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? 1 : 0, b.g.n_nodes, b.g.d, s));
+    T* t_next = (fuse && k + 1 < degree) ? t : nullptr;
+    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? 1 : 0, b.g.n_nodes, b.g.d, b.mask, t_next, s));
   }
   return PF_OK;
 }
@@ -1148,9 +1166,9 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
 }
 
 // ---------------------------------------------------------------------------------- autotuner
-// Candidates of the Q1 cell loop: (variant, chunk).  Variant 1 (16x4 tiles) is 3D only.
-static const int kCand[][2] = {{2, -1}, {0, 8}, {0, 16}, {0, 32}, {1, 8}, {1, 16}, {1, 32}};
-static const int kNCand = 7;
+// Candidates of the Q1 cell loop: (variant, chunk).  Variants 1 (16x4 tiles) and 3 (LDS bricks) are 3D only.
+static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {1, 4}, {1, 8}, {1, 16}};
+static const int kNCand = 9;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];
@@ -1170,7 +1188,7 @@ static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
       double best = 1e300;
       int bv = -1, bz = -1;
       for (int k = 0; k < kNCand && st == PF_OK; ++k) {
-        if (kCand[k][0] == 1 && b.g.d != 3) {
+        if ((kCand[k][0] == 1 || kCand[k][0] == 3) && b.g.d != 3) {
           b.tune_us[pi][mi][k] = -1.0;
           continue;
         }
@@ -1246,7 +1264,7 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
   int pi, mi;
   PFF_TRY(tuning_index(ctx, level, prec, mode, &pi, &mi));
   if (variant < -1 || variant >= kQ1Variants || zc > 4096) {
-    set_error("variant must be in [-1, 2] and zc <= 4096");
+    set_error("variant must be in [-1, 4] and zc <= 4096");
     return PF_ERR_INVALID_ARG;
   }
   ctx->lev[level].variant[pi][mi] = variant;

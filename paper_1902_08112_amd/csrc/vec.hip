@@ -107,7 +107,7 @@ pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s) {
 // diag holds diag(B~) (1 on constrained rows).
 template <typename T>
 __global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1u, T c2u, T c1p, T c2p, int first,
-                            int64_t nn, int d) {
+                            int64_t nn, int d, const uint8_t* mask, T* t_next) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int64_t nu = (int64_t)d * nn;
   GRID_STRIDE(i, n) {
@@ -124,13 +124,17 @@ __global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1
     }
     dv[i] = dn;
     x[i] += dn;
+    if (t_next) {  // y = Pi_C dv of the next operator apply (t is consumed above)
+      const int c = (int)(i / nn);
+      t_next[i] = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? dn : T(0);
+    }
   }
 }
 template <typename T>
 pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int first, int64_t nn, int d, hipStream_t s) {
+                        int first, int64_t nn, int d, const uint8_t* mask, T* t_next, hipStream_t s) {
   k_cheb_step<T><<<nblocks((d + 1) * nn), 256, 0, s>>>(res, t, dv, x, diag, (T)c1[0], (T)c2[0], (T)c1[1],
-                                                       (T)c2[1], first, nn, d);
+                                                       (T)c2[1], first, nn, d, mask, t_next);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
@@ -469,7 +473,7 @@ pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const d
   template pf_status vec_axpby<T>(T*, T, const T*, T, int64_t, hipStream_t);                                   \
   template pf_status vec_sub<T>(T*, const T*, const T*, int64_t, hipStream_t);                                 \
   template pf_status vec_cheb_step<T>(T*, const T*, T*, T*, const T*, const double*, const double*, int, int64_t, \
-                                      int, hipStream_t);
+                                      int, const uint8_t*, T*, hipStream_t);
 INST_T(double)
 INST_T(float)
 template pf_status vec_cast<double, float>(float*, const double*, int64_t, hipStream_t);

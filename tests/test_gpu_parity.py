@@ -52,12 +52,13 @@ def test_apply_f64_all_levels(name):
 
 @pytest.mark.parametrize("name", ["cfg1_2d_q1_32", "small3d", "small_lshape"])
 def test_apply_every_kernel_variant(name):
-    """Each Q1 cell-loop shape the autotuner can pick (atomic, 8x8 / 16x4 marching tiles with
-    full and ragged chunks) matches the oracle, in both operators and precisions."""
+    """Each Q1 cell-loop shape the autotuner can pick (atomic, split cells, LDS bricks with
+    ragged edge bricks, 8x8 / 16x4 marching tiles with full and ragged chunks) matches the oracle, in both
+    operators and precisions."""
     from paper_1902_08112_amd import pff
     s, U, phit, act, H, S = setup_case(name, seed=29)
     torch = __import__("torch")
-    variants = [(2, -1), (0, 8), (0, 3), (0, 1)] + ([(1, 8), (1, 5)] if s["dim"] == 3 else [])
+    variants = [(2, -1), (3, -1), (4, -1), (0, 8), (0, 3), (0, 1)] + ([(1, 8), (1, 5)] if s["dim"] == 3 else [])
     for l in range(s["n_levels"]):
         x = np.random.default_rng(300 + l).uniform(-1, 1, H.levels[l].n_dofs)
         refG, refB = H.mg[l].G @ x, H.mg[l].B @ x
@@ -80,7 +81,7 @@ def test_autotune_report_and_cache(tmp_path):
     assert len(rep["levels"]) == s["n_levels"]
     for lv in rep["levels"]:
         for ch in lv["choices"]:
-            assert ch["variant"] in (0, 1, 2)
+            assert ch["variant"] in (0, 1, 2, 3, 4)
             times = [t for v, z, t in ch["us"] if t > 0]
             assert len(times) >= 4 and min(times) > 0
     # cached choices are restored without timing
