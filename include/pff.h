@@ -239,10 +239,15 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
 /* JSON text of the choices and measured candidate times (microseconds per apply). */
 pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len);
 
-/* Graph replay of the V-cycle (default on): the first V-cycle after a change
+/* Graph replay of the V-cycle (default off): the first V-cycle after a change
  * of level data, eigenvalue bounds or tuning is captured into a hipGraph on a
  * private stream and replayed on the caller's stream afterwards (pf_vcycle and
- * the FGMRES of pf_newton_step).  enable = 0 launches every kernel directly. */
+ * the FGMRES of pf_newton_step).  enable = 0 launches every kernel directly.
+ * The Chebyshev coefficients are kernel arguments of the capture, so every
+ * new linearization re-captures; within one Newton step (a handful of
+ * V-cycles) the capture costs more than the replays save, so eager launches
+ * are the default.  Callers that run many V-cycles per linearization (or that
+ * need the launch sequence fixed) enable it. */
 pf_status pf_set_graphs(pf_ctx* ctx, int enable);
 
 /* Change the V-cycle precision used by pf_newton_step (PF_F64 or PF_F32). */

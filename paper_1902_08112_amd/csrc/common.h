@@ -132,12 +132,16 @@ pf_status vec_axpby(T* y, T a, const T* x, T b, int64_t n, hipStream_t s);
 template <typename T>
 pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s);
 // Chebyshev step (per block coefficients c1[2], c2[2]; blocks u / phi):
-//   first:  d = c2 * Dinv * res;           x += d
-//   other:  res -= t; d = c1*d + c2*Dinv*res; x += d
-// t_next (may alias t, or nullptr): t_next = Pi_C d, the starting value of the next apply
+//   mode 0: res -= t;      d = c1*d + c2*Dinv*res; x += d
+//   mode 1: res = b;       d = c2*Dinv*res;        x = d    (x = 0 before)
+//   mode 2: res = b - t;   d = c2*Dinv*res;        x += d   (t = G~ x)
+//   mode 3: res as given;  d = c2*Dinv*res;        x += d
+// t_next (may alias t, or nullptr): t_next = Pi_C d (Pi_C x_new if next_of_x), the
+// starting value of the next operator apply
 template <typename T>
 pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int first, int64_t nn, int d, const uint8_t* mask, T* t_next, hipStream_t s);
+                        int mode, int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b,
+                        hipStream_t s);
 // dots per block: out[0] = sum over u-block of x*y, out[1] over the phi-block (FP64 accumulation)
 pf_status dot_blocks(const double* x, const double* y, int64_t nn, int d, double* d_partials, double* h_out,
                      hipStream_t s);
@@ -195,10 +199,11 @@ pf_status inject(const Geom& gc, const Geom& gf, const T* fine, T* coarse, int n
 // coarse_mask[j] = fine_mask[inj(j)] | base[j]
 pf_status inject_mask(const Geom& gc, const Geom& gf, const uint8_t* fine, const uint8_t* base, uint8_t* coarse,
                       hipStream_t s);
-// restriction out_c = [mask_c] P^T in_f ; in_f read as is
+// restriction out_c = [mask_c] P^T v with v = in_f, or v = in_f - sub_f (formed in Tin) when sub_f
+// is set (the residual b - G~ x restricted without storing it)
 template <typename Tin, typename Tout>
-pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, Tout* out_c, const uint8_t* mask_c,
-                       hipStream_t s);
+pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, const Tin* sub_f, Tout* out_c,
+                       const uint8_t* mask_c, hipStream_t s);
 // prolongation: out_f = (add ? out_f : 0) + [mask_f] P in_c
 template <typename Tin, typename Tout>
 pf_status prolong_vec(const Geom& gc, const Geom& gf, const Tin* in_c, Tout* out_f, const uint8_t* mask_f, int add,

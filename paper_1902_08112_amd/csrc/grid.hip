@@ -84,30 +84,30 @@ __global__ void k_prolong(G3 c, G3 f, const Tin* __restrict__ in_c, Tout* __rest
   }
 }
 template <int D, int P, typename Tin, typename Tout>
-__global__ void k_restrict(G3 c, G3 f, const Tin* __restrict__ in_f, Tout* __restrict__ out_c,
-                           const uint8_t* __restrict__ mask_c) {
+__global__ void k_restrict(G3 c, G3 f, const Tin* __restrict__ in_f, const Tin* __restrict__ sub_f,
+                           Tout* __restrict__ out_c, const uint8_t* __restrict__ mask_c) {
   const int64_t n = (int64_t)(D + 1) * c.n_nodes;
   GRID_STRIDE(t, n) {
     const int comp = (int)(t / c.n_nodes);
     const int64_t j = t - (int64_t)comp * c.n_nodes;
     const bool con = mask_c && (mask_c[j] & mask_bit(comp, D));
-    out_c[t] = (Tout)(con ? 0.0 : restrict_dof<D, P, Tin>(c, f, j, comp, in_f));
+    out_c[t] = (Tout)(con ? 0.0 : restrict_dof<D, P, Tin>(c, f, j, comp, in_f, sub_f));
   }
 }
 
 template <typename Tin, typename Tout>
-pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, Tout* out_c, const uint8_t* mask_c,
-                       hipStream_t s) {
+pf_status restrict_vec(const Geom& gc, const Geom& gf, const Tin* in_f, const Tin* sub_f, Tout* out_c,
+                       const uint8_t* mask_c, hipStream_t s) {
   const int64_t n = gc.n_dofs;
   const G3 c = g3(gc), f = g3(gf);
   if (gf.d == 2 && gf.p == 1)
-    k_restrict<2, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+    k_restrict<2, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, sub_f, out_c, mask_c);
   else if (gf.d == 2)
-    k_restrict<2, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+    k_restrict<2, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, sub_f, out_c, mask_c);
   else if (gf.p == 1)
-    k_restrict<3, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+    k_restrict<3, 1, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, sub_f, out_c, mask_c);
   else
-    k_restrict<3, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, out_c, mask_c);
+    k_restrict<3, 2, Tin, Tout><<<nblk(n), 256, 0, s>>>(c, f, in_f, sub_f, out_c, mask_c);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
@@ -128,7 +128,7 @@ pf_status prolong_vec(const Geom& gc, const Geom& gf, const Tin* in_c, Tout* out
   return PF_OK;
 }
 #define INST_TR(A, B)                                                                                    \
-  template pf_status restrict_vec<A, B>(const Geom&, const Geom&, const A*, B*, const uint8_t*, hipStream_t); \
+  template pf_status restrict_vec<A, B>(const Geom&, const Geom&, const A*, const A*, B*, const uint8_t*, hipStream_t); \
   template pf_status prolong_vec<A, B>(const Geom&, const Geom&, const A*, B*, const uint8_t*, int, hipStream_t);
 INST_TR(double, double)
 INST_TR(float, float)

@@ -242,9 +242,10 @@ __device__ inline void prolong_taps(int fi, int Nc, int64_t stride, double w[P +
   }
 }
 
-// (P^T in_f) at coarse node j, component comp
+// (P^T v) at coarse node j, component comp; v = in_f, or in_f - sub_f (formed in Tin) if sub_f
 template <int D, int P, typename Tin>
-__device__ inline double restrict_dof(const G3& c, const G3& f, int64_t j, int comp, const Tin* __restrict__ in_f) {
+__device__ inline double restrict_dof(const G3& c, const G3& f, int64_t j, int comp, const Tin* __restrict__ in_f,
+                                      const Tin* __restrict__ sub_f = nullptr) {
   constexpr int T = 4 * P - 1;
   int idx[3];
   node_idx(c, j, idx);
@@ -254,6 +255,8 @@ __device__ inline double restrict_dof(const G3& c, const G3& f, int64_t j, int c
   restrict_taps<P>(idx[1], f.nn[1], c.N[1], f.ns[1], wy, oy);
   if constexpr (D == 3) restrict_taps<P>(idx[2], f.nn[2], c.N[2], f.ns[2], wz, oz);
   const Tin* src = in_f + (int64_t)comp * f.n_nodes;
+  const Tin* sub = sub_f ? sub_f + (int64_t)comp * f.n_nodes : nullptr;
+  auto val = [&](int64_t k) -> double { return sub ? (double)(Tin)(src[k] - sub[k]) : (double)src[k]; };
   double acc = 0.0;
 #pragma unroll
   for (int a = 0; a < T; ++a)
@@ -263,9 +266,9 @@ __device__ inline double restrict_dof(const G3& c, const G3& f, int64_t j, int c
       if constexpr (D == 3) {
 #pragma unroll
         for (int e = 0; e < T; ++e)
-          if (wab * wz[e] != 0.0) acc += wab * wz[e] * (double)src[ox[a] + oy[b] + oz[e]];
+          if (wab * wz[e] != 0.0) acc += wab * wz[e] * val(ox[a] + oy[b] + oz[e]);
       } else {
-        if (wab != 0.0) acc += wab * (double)src[ox[a] + oy[b]];
+        if (wab != 0.0) acc += wab * val(ox[a] + oy[b]);
       }
     }
   return acc;

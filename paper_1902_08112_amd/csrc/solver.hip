@@ -118,6 +118,11 @@ static double tridiag_eig(const std::vector<double>& a, const std::vector<double
 
 using namespace pff;
 
+// reduction scratch of one concurrent level task (partials of two segments + results)
+constexpr size_t kPartStride = 2 * kRedMaxBlocks + 256;
+// FGMRES scalars per Arnoldi step, device dscal[0 .. kHostScal): h1 at 0, h2 at 256, |w|^2 at 512
+constexpr int kHostScal = 520;
+
 struct LevelBuf {
   Geom g;
   double *U = nullptr, *phit = nullptr, *diag = nullptr;
@@ -148,10 +153,17 @@ struct pf_ctx {
   // level data, eigenvalue bounds or kernel tuning
   double *vin = nullptr, *vout = nullptr;
   hipStream_t cap_stream = nullptr;
+  // per-level helper streams of the linearization set-up (diagonals and eigenvalue CGs of
+  // all levels run concurrently), their join events, and per-level reduction scratch
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_ev;
+  hipEvent_t fork_ev = nullptr;
+  double* part_lev = nullptr;
+  double* host_scal = nullptr;  // pinned host copy of the FGMRES scalars (kHostScal doubles)
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
-  bool use_graphs = true;
+  bool use_graphs = false;  // eager launches: a capture per linearization costs more than replays save
   bool fused_coarse = true;  // coarse Chebyshev solve in one single-workgroup launch
   void drop_graphs() {
     for (int k = 0; k < 2; ++k) {
@@ -165,6 +177,10 @@ struct pf_ctx {
   ~pf_ctx() {
     drop_graphs();
     if (cap_stream) hipStreamDestroy(cap_stream);
+    for (hipStream_t a : aux) hipStreamDestroy(a);
+    for (hipEvent_t e : aux_ev) hipEventDestroy(e);
+    if (fork_ev) hipEventDestroy(fork_ev);
+    if (host_scal) hipHostFree(host_scal);
   }
   bool has_extra = false, has_lin = false;
   size_t ws_bytes = 0;
@@ -334,6 +350,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* part_md = cv.take<double>((size_t)256 * (mr + 2));
   double* dscal = cv.take<double>(1024);
   EigDev* eigdev = cv.take<EigDev>(L);
+  double* part_lev = cv.take<double>((size_t)L * kPartStride);
   double* vin = cv.take<double>(nd);
   double* vout = cv.take<double>(nd);
   if (c) {
@@ -352,6 +369,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->part_md = part_md;
     c->dscal = dscal;
     c->eigdev = eigdev;
+    c->part_lev = part_lev;
     c->vin = vin;
     c->vout = vout;
   }
@@ -412,10 +430,13 @@ ChebCoef cheb_coefs(double lo, double hi, int degree) {
   return r;
 }
 
-// x += Cheb_B(res) with per-block intervals; res is overwritten; uses vd, vt of the level
+// x += Cheb_B(r) with per-block intervals, starting from r as selected by first_mode
+// (vec_cheb_step: 1 = b with x = 0, 2 = b - t with t = G~ x, 3 = res as given); res is
+// overwritten; uses vd, vt of the level.  tail_init: the last step leaves t = Pi_C x, the
+// start of a following G~ x apply.
 template <typename T>
 pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2], const double hi[2], int degree,
-                   hipStream_t s) {
+                   int first_mode, const T* bvec, bool tail_init, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   const ChebCoef cu = cheb_coefs(lo[0], hi[0], degree), cpz = cheb_coefs(lo[1], hi[1], degree);
   T* dv = (T*)b.vd;
@@ -426,29 +447,33 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
   for (int k = 0; k < degree; ++k) {
     if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s, fuse));
     const double c1[2] = {cu.c1[k], cpz.c1[k]}, c2[2] = {cu.c2[k], cpz.c2[k]};
-    T* t_next = (fuse && k + 1 < degree) ? t : nullptr;
-    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? 1 : 0, b.g.n_nodes, b.g.d, b.mask, t_next, s));
+    T* t_next = nullptr;
+    int next_of_x = 0;
+    if (k + 1 < degree) {
+      if (fuse) t_next = t;
+    } else if (tail_init) {
+      t_next = t;
+      next_of_x = 1;
+    }
+    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? first_mode : 0, b.g.n_nodes, b.g.d, b.mask,
+                             t_next, next_of_x, bvec, s));
   }
   return PF_OK;
 }
 
-// one smoothing step x += Cheb_B(b - G~ x)
+// one smoothing step x += Cheb_B(b - G~ x); x_zero: x = 0 on entry (x is not read).
+// tail_init: leave t = Pi_C x for a following G~ x apply.
 template <typename T>
-pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, hipStream_t s) {
+pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, bool tail_init, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   T* bb = (T*)b.vb;
   T* x = (T*)b.vx;
   T* r = (T*)b.vr;
-  if (x_zero) {
-    PFF_TRY(vec_sub<T>(r, bb, x, b.g.n_dofs, s));  // x == 0: r = b (a kernel, no memcpy node in graphs)
-  } else {
-    PFF_TRY(level_apply(c, l, prec, MODE_APPLY, x, b.vt, s));
-    PFF_TRY(vec_sub<T>(r, bb, (T*)b.vt, b.g.n_dofs, s));
-  }
+  if (!x_zero) PFF_TRY(level_apply(c, l, prec, MODE_APPLY, x, b.vt, s));
   const pf_options& o = c->opt;
   const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
   const double lo[2] = {hi[0] / o.cheb_ratio, hi[1] / o.cheb_ratio};
-  return cheb_run<T>(c, l, prec, r, x, lo, hi, o.cheb_degree, s);
+  return cheb_run<T>(c, l, prec, r, x, lo, hi, o.cheb_degree, x_zero ? 1 : 2, bb, tail_init, s);
 }
 
 pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
@@ -466,15 +491,10 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
                                 cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, bb, x, r, s, &handled));
     if (handled) return PF_OK;
   }
-  PFF_TRY(vec_fill<double>(x, 0.0, b.g.n_dofs, s));
   for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
-    if (sw == 0) {
-      PFF_TRY(vec_sub<double>(r, bb, x, b.g.n_dofs, s));  // x == 0
-    } else {
-      PFF_TRY(level_apply(c, 0, PF_F64, MODE_APPLY, x, b.vt, s));
-      PFF_TRY(vec_sub<double>(r, bb, (double*)b.vt, b.g.n_dofs, s));
-    }
-    PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, s));
+    if (sw > 0) PFF_TRY(level_apply(c, 0, PF_F64, MODE_APPLY, x, b.vt, s));
+    // sweep 0 starts from x = 0 (r = b), later sweeps from r = b - G~ x
+    PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, sw == 0 ? 1 : 2, bb, false, s));
   }
   return PF_OK;
 }
@@ -483,7 +503,8 @@ template <typename Tf, typename Tc>
 pf_status restrict_to(pf_ctx* c, int l, hipStream_t s) {
   LevelBuf& f = c->lev[l];
   LevelBuf& co = c->lev[l - 1];
-  return restrict_vec<Tf, Tc>(co.g, f.g, (const Tf*)f.vr, (Tc*)co.vb, co.mask, s);
+  // residual r = b - G~ x of the level (b in vb, G~ x in vt), restricted without being stored
+  return restrict_vec<Tf, Tc>(co.g, f.g, (const Tf*)f.vb, (const Tf*)f.vt, (Tc*)co.vb, co.mask, s);
 }
 template <typename Tc, typename Tf>
 pf_status prolong_add(pf_ctx* c, int l, hipStream_t s) {
@@ -496,26 +517,25 @@ pf_status vcycle_level(pf_ctx* c, int l, int vprec, hipStream_t s) {
   if (l == 0) return coarse_solve(c, s);
   const int pl = level_prec(c, l, vprec), pc = level_prec(c, l - 1, vprec);
   LevelBuf& b = c->lev[l];
+  // pre-smoothing from x = 0; its last step leaves t = Pi_C x when the residual apply needs it,
+  // and the residual b - G~ x is formed inside the restriction
+  const bool pre_init = apply_needs_preset(c, l, pl, MODE_APPLY);
   if (pl == PF_F64) {
-    PFF_TRY(vec_fill<double>((double*)b.vx, 0.0, b.g.n_dofs, s));
-    PFF_TRY(smooth<double>(c, l, pl, true, s));
-    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s));
-    PFF_TRY(vec_sub<double>((double*)b.vr, (double*)b.vb, (double*)b.vt, b.g.n_dofs, s));
+    PFF_TRY(smooth<double>(c, l, pl, true, pre_init, s));
+    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s, pre_init));
     PFF_TRY(pc == PF_F64 ? restrict_to<double, double>(c, l, s) : restrict_to<double, float>(c, l, s));
   } else {
-    PFF_TRY(vec_fill<float>((float*)b.vx, 0.0f, b.g.n_dofs, s));
-    PFF_TRY(smooth<float>(c, l, pl, true, s));
-    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s));
-    PFF_TRY(vec_sub<float>((float*)b.vr, (float*)b.vb, (float*)b.vt, b.g.n_dofs, s));
+    PFF_TRY(smooth<float>(c, l, pl, true, pre_init, s));
+    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s, pre_init));
     PFF_TRY(pc == PF_F64 ? restrict_to<float, double>(c, l, s) : restrict_to<float, float>(c, l, s));
   }
   PFF_TRY(vcycle_level(c, l - 1, vprec, s));
   if (pl == PF_F64) {
     PFF_TRY(pc == PF_F64 ? prolong_add<double, double>(c, l, s) : prolong_add<float, double>(c, l, s));
-    PFF_TRY(smooth<double>(c, l, pl, false, s));
+    PFF_TRY(smooth<double>(c, l, pl, false, false, s));
   } else {
     PFF_TRY(pc == PF_F64 ? prolong_add<double, float>(c, l, s) : prolong_add<float, float>(c, l, s));
-    PFF_TRY(smooth<float>(c, l, pl, false, s));
+    PFF_TRY(smooth<float>(c, l, pl, false, false, s));
   }
   return PF_OK;
 }
@@ -577,7 +597,7 @@ pf_status vcycle_any(pf_ctx* c, int vprec, const double* r, double* z, hipStream
 // ---------------------------------------------------------------------------
 // Launch the Jacobi-PCG of level l (both diagonal blocks, lockstep); the
 // coefficients stay in c->eigdev[l] until eig_from_cg reads them.
-pf_status launch_eig_cg(pf_ctx* c, int l, hipStream_t s) {
+pf_status launch_eig_cg(pf_ctx* c, int l, double* part, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   const Geom& g = b.g;
   double* r = (double*)b.vr;
@@ -589,11 +609,11 @@ pf_status launch_eig_cg(pf_ctx* c, int l, hipStream_t s) {
   const uint64_t su = seed + (uint64_t)l * 0x1000003ull + 0ull * 0x10001ull;
   const uint64_t sp = seed + (uint64_t)l * 0x1000003ull + 1ull * 0x10001ull;
   PFF_TRY(eig_start_vector(r, b.mask, g.n_nodes, g.d, su, sp, s));
-  PFF_TRY(eig_cg_begin(r, z, p, b.diag, b.mask, g.n_nodes, g.d, c->part, st, s));
+  PFF_TRY(eig_cg_begin(r, z, p, b.diag, b.mask, g.n_nodes, g.d, part, st, s));
   for (int it = 0; it < c->opt.eig_cg_steps; ++it) {
     PFF_TRY(level_apply(c, l, PF_F64, MODE_BLOCK, p, Ap, s));
-    PFF_TRY(eig_cg_alpha(p, Ap, g.n_nodes, g.d, c->part, st, s));
-    PFF_TRY(eig_cg_beta(r, Ap, z, p, b.diag, b.mask, g.n_nodes, g.d, c->part, st, s));
+    PFF_TRY(eig_cg_alpha(p, Ap, g.n_nodes, g.d, part, st, s));
+    PFF_TRY(eig_cg_beta(r, Ap, z, p, b.diag, b.mask, g.n_nodes, g.d, part, st, s));
   }
   return PF_OK;
 }
@@ -617,21 +637,45 @@ void eig_from_cg(const EigDev& e, double eig[4]) {
   }
 }
 
-// every level without fixed bounds: launch all CG runs, then one read-back
-pf_status estimate_eigs_all(pf_ctx* c, hipStream_t s) {
+// read back the CG coefficients of every level without fixed bounds (after the level tasks)
+pf_status eig_readback(pf_ctx* c, hipStream_t s) {
   const int L = (int)c->lev.size();
   bool any = false;
-  for (int l = 0; l < L; ++l)
-    if (!c->lev[l].eig_fixed) {
-      PFF_TRY(launch_eig_cg(c, l, s));
-      any = true;
-    }
+  for (int l = 0; l < L; ++l) any = any || !c->lev[l].eig_fixed;
   if (!any) return PF_OK;
   std::vector<EigDev> h(L);
   PFF_HIP(hipMemcpyAsync(h.data(), c->eigdev, sizeof(EigDev) * L, hipMemcpyDeviceToHost, s));
   PFF_HIP(hipStreamSynchronize(s));
   for (int l = 0; l < L; ++l)
     if (!c->lev[l].eig_fixed) eig_from_cg(h[l], c->lev[l].eig);
+  return PF_OK;
+}
+
+// helper streams and events of the level tasks (created on first use)
+pf_status ensure_aux(pf_ctx* c) {
+  const size_t L = c->lev.size();
+  if (!c->fork_ev) PFF_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+  while (c->aux.size() < L) {
+    hipStream_t a;
+    PFF_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    c->aux.push_back(a);
+  }
+  while (c->aux_ev.size() < L) {
+    hipEvent_t e;
+    PFF_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->aux_ev.push_back(e);
+  }
+  return PF_OK;
+}
+
+// per-level set-up task: diagonal of B~, FP32 copies, eigenvalue CG
+pf_status level_task(pf_ctx* c, int l, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  PFF_TRY(apply_op<double>(b.g, cparams(c, l), MODE_DIAG, nullptr, b.U, b.phit, b.mask, b.diag, s));
+  PFF_TRY(vec_cast<double, float>(b.U32, b.U, b.g.n_dofs, s));
+  PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
+  PFF_TRY(vec_cast<double, float>(b.diag32, b.diag, b.g.n_dofs, s));
+  if (!b.eig_fixed) PFF_TRY(launch_eig_cg(c, l, c->part_lev + (size_t)l * kPartStride, s));
   return PF_OK;
 }
 
@@ -648,14 +692,18 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
     PFF_TRY(inject<double>(co.g, fi.g, fi.phit, co.phit, 1, s));
     PFF_TRY(inject_mask(co.g, fi.g, fi.mask, co.base, co.mask, s));
   }
-  for (int l = 0; l <= L; ++l) {
-    LevelBuf& b = c->lev[l];
-    PFF_TRY(apply_op<double>(b.g, cparams(c, l), MODE_DIAG, nullptr, b.U, b.phit, b.mask, b.diag, s));
-    PFF_TRY(vec_cast<double, float>(b.U32, b.U, b.g.n_dofs, s));
-    PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
-    PFF_TRY(vec_cast<double, float>(b.diag32, b.diag, b.g.n_dofs, s));
+  // the levels are independent from here on: one task per level on its own stream, the
+  // finest on the caller's stream, joined before the coefficients are read back
+  PFF_TRY(ensure_aux(c));
+  PFF_HIP(hipEventRecord(c->fork_ev, s));
+  for (int l = 0; l < L; ++l) {
+    PFF_HIP(hipStreamWaitEvent(c->aux[l], c->fork_ev, 0));
+    PFF_TRY(level_task(c, l, c->aux[l]));
+    PFF_HIP(hipEventRecord(c->aux_ev[l], c->aux[l]));
   }
-  PFF_TRY(estimate_eigs_all(c, s));
+  PFF_TRY(level_task(c, L, s));
+  for (int l = 0; l < L; ++l) PFF_HIP(hipStreamWaitEvent(s, c->aux_ev[l], 0));
+  PFF_TRY(eig_readback(c, s));
   PFF_HIP(hipStreamSynchronize(s));
   c->has_lin = true;
   c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle
@@ -686,7 +734,9 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
   PFF_TRY(true_res(&beta));
   int total = 0;
   std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
-  std::vector<double> hbuf(2 * (m + 1) + 2);
+  std::vector<double> hbuf(2);
+  if (!c->host_scal) PFF_HIP(hipHostMalloc((void**)&c->host_scal, sizeof(double) * kHostScal, hipHostMallocDefault));
+  double* hs = c->host_scal;
   while (beta > tol && total < c->opt.gmres_max_iter) {
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
@@ -713,12 +763,11 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
       PFF_TRY(multi_axpy(w, c->V, n, j + 1, h2, n, -1.0, s));
       PFF_TRY(nrm2_dev(w, n, c->part, nr, s));
       PFF_TRY(vec_scale_inv_sqrt(w, w, nr, n, s));
-      PFF_HIP(hipMemcpyAsync(hbuf.data(), c->dscal, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-      PFF_HIP(hipMemcpyAsync(hbuf.data() + (m + 1), h2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, s));
-      PFF_HIP(hipMemcpyAsync(hbuf.data() + 2 * (m + 1), nr, sizeof(double), hipMemcpyDeviceToHost, s));
+      // one copy of both Gram-Schmidt passes and the norm into pinned memory
+      PFF_HIP(hipMemcpyAsync(hs, c->dscal, sizeof(double) * kHostScal, hipMemcpyDeviceToHost, s));
       PFF_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hbuf[i] + hbuf[(m + 1) + i];
-      H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(0.0, hbuf[2 * (m + 1)]));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hs[i] + hs[256 + i];
+      H[(size_t)(j + 1) * m + j] = std::sqrt(std::max(0.0, hs[512]));
       for (int i = 0; i < j; ++i) {
         const double a = H[(size_t)i * m + j], bq = H[(size_t)(i + 1) * m + j];
         H[(size_t)i * m + j] = cs[i] * a + sn[i] * bq;
@@ -1027,7 +1076,7 @@ pf_status pf_transfer(pf_ctx* ctx, int level, int op, const double* d_in, double
   const Geom& gf = ctx->lev[level].g;
   const Geom& gc = ctx->lev[level - 1].g;
   hipStream_t s = st(stream);
-  if (op == 0) return restrict_vec<double, double>(gc, gf, d_in, d_out, nullptr, s);
+  if (op == 0) return restrict_vec<double, double>(gc, gf, d_in, nullptr, d_out, nullptr, s);
   if (op == 1) return prolong_vec<double, double>(gc, gf, d_in, d_out, nullptr, 0, s);
   if (op == 2) return inject<double>(gc, gf, d_in, d_out, gf.d + 1, s);
   set_error("op must be 0 (restrict), 1 (prolong) or 2 (inject)");

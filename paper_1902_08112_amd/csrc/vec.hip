@@ -104,37 +104,45 @@ pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s) {
 }
 
 // Chebyshev-Jacobi step of the smoother (three-term recurrence, Sec. 3.2.1).
-// diag holds diag(B~) (1 on constrained rows).
+// diag holds diag(B~) (1 on constrained rows).  mode selects the residual the
+// step starts from: 0 = res - t (t = B~ d of the previous direction);
+// 1 = b with x = 0 (x is written, not read); 2 = b - t with t = G~ x;
+// 3 = res as given.  t_next, if set, receives Pi_C of the new direction (or of
+// the new x when next_of_x) as the starting value of the next operator apply.
 template <typename T>
-__global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1u, T c2u, T c1p, T c2p, int first,
-                            int64_t nn, int d, const uint8_t* mask, T* t_next) {
+__global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1u, T c2u, T c1p, T c2p, int mode,
+                            int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int64_t nu = (int64_t)d * nn;
   GRID_STRIDE(i, n) {
     const bool phi = i >= nu;
     const T c1 = phi ? c1p : c1u, c2 = phi ? c2p : c2u;
-    T r = res[i];
-    T dn;
-    if (first) {
-      dn = c2 * r / diag[i];
-    } else {
-      r -= t[i];
+    T r, dn, xn;
+    if (mode == 0) {
+      r = res[i] - t[i];
       res[i] = r;
       dn = c1 * dv[i] + c2 * r / diag[i];
+      xn = x[i] + dn;
+    } else {
+      r = mode == 1 ? b[i] : (mode == 2 ? b[i] - t[i] : res[i]);
+      if (mode != 3) res[i] = r;
+      dn = c2 * r / diag[i];
+      xn = mode == 1 ? dn : x[i] + dn;
     }
     dv[i] = dn;
-    x[i] += dn;
-    if (t_next) {  // y = Pi_C dv of the next operator apply (t is consumed above)
+    x[i] = xn;
+    if (t_next) {
       const int c = (int)(i / nn);
-      t_next[i] = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? dn : T(0);
+      t_next[i] = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? (next_of_x ? xn : dn) : T(0);
     }
   }
 }
 template <typename T>
 pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int first, int64_t nn, int d, const uint8_t* mask, T* t_next, hipStream_t s) {
+                        int mode, int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b,
+                        hipStream_t s) {
   k_cheb_step<T><<<nblocks((d + 1) * nn), 256, 0, s>>>(res, t, dv, x, diag, (T)c1[0], (T)c2[0], (T)c1[1],
-                                                       (T)c2[1], first, nn, d, mask, t_next);
+                                                       (T)c2[1], mode, nn, d, mask, t_next, next_of_x, b);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
@@ -473,7 +481,7 @@ pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const d
   template pf_status vec_axpby<T>(T*, T, const T*, T, int64_t, hipStream_t);                                   \
   template pf_status vec_sub<T>(T*, const T*, const T*, int64_t, hipStream_t);                                 \
   template pf_status vec_cheb_step<T>(T*, const T*, T*, T*, const T*, const double*, const double*, int, int64_t, \
-                                      int, const uint8_t*, T*, hipStream_t);
+                                      int, const uint8_t*, T*, int, const T*, hipStream_t);
 INST_T(double)
 INST_T(float)
 template pf_status vec_cast<double, float>(float*, const double*, int64_t, hipStream_t);
