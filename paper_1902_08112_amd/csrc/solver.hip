@@ -23,6 +23,10 @@ pf_status launch_cell_q1_d(const Geom&, const CellParams&, int, const double*, c
                            const uint8_t*, double*, hipStream_t, bool* handled);
 pf_status launch_cell_q1_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
                            const uint8_t*, float*, hipStream_t, bool* handled);
+pf_status launch_cell_q2_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
+                           const uint8_t*, double*, hipStream_t, bool* handled);
+pf_status launch_cell_q2_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
+                           const uint8_t*, float*, hipStream_t, bool* handled);
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
@@ -34,6 +38,8 @@ pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, con
   bool handled = false;
   pf_status st = launch_cell_q1_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
+  st = launch_cell_q2_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
+  if (handled) return st;
   return launch_cell_generic_d(g, cp, mode, x, U, phit, mask, y, s);
 }
 template <>
@@ -41,6 +47,8 @@ pf_status launch_cell<float>(const Geom& g, const CellParams& cp, int mode, cons
                              const float* phit, const uint8_t* mask, float* y, hipStream_t s) {
   bool handled = false;
   pf_status st = launch_cell_q1_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
+  if (handled) return st;
+  st = launch_cell_q2_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
   return launch_cell_generic_f(g, cp, mode, x, U, phit, mask, y, s);
 }
