@@ -9,10 +9,16 @@ each time from the same iterate U_k (the reset copy is inside the timed loop).
 
 value = fine-level DoFs per second of Newton steps with the plain FP64 V-cycle
 (the workload's own setting); the FP32-V-cycle step time and the speedup are
-reported beside it.  The roofline entry is the FP64 Jacobian apply on the
-finest level (dominant kernel), timed with HIP events on the stream the
-library launches on.  cpu_baseline: the FP64 oracle's Newton step on a 16^3
-sample of the same workload (same crack, material and eps), one core.
+reported beside it.  The roofline entry is the FP64 Jacobian cell kernel on
+the finest level (dominant kernel): the library brackets each of its launches
+inside the timed FP64 Newton steps with HIP events on the launch stream
+(pf_set_kernel_timing), and achieved = algorithmic flops per launch / mean
+launch duration.  traffic = HBM bytes per launch from the committed rocprofv3
+FETCH_SIZE / WRITE_SIZE summary of this command (profiles/), while the
+kernel's sources are unchanged.  After the timed region a plain device copy of
+one fine-level vector runs (the counters' calibration).  cpu_baseline: the
+FP64 oracle's Newton step on a 32^3 sample of the same workload (same crack,
+material and eps), one core.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
 """
@@ -35,6 +41,34 @@ FLOP_PER_CELL = {(2, 1): 656.0, (3, 1): 2496.0, (3, 2): 12312.0, (2, 2): 2124.0}
 BYTES_PER_DOF_F64 = {2: 8 * 3 + (8 + 1) / 3.0, 3: 8 * 3 + (8 + 1) / 4.0}
 
 
+# kernel of the finest-level FP64 Jacobian apply for a tuning variant (as rocprofv3 names it)
+def kernel_name(dim, degree, variant):
+    if degree == 2:
+        return "k_q2_3d<double, 0>" if dim == 3 else "k_cell_generic<2, 2, double, 0>"
+    if dim == 2:
+        return {0: "k_q1_2d<double, 0>", 2: "k_q1_2d_atomic<double, 0>",
+                4: "k_q1_split<2, double, 0>"}.get(variant, "k_q1_2d<double, 0>")
+    return {0: "k_q1_3d<double, 0, 8, 8>", 1: "k_q1_3d<double, 0, 16, 4>", 2: "k_q1_3d_atomic<double, 0>",
+            3: "k_q1_3d_brick<double, 0>", 4: "k_q1_split<3, double, 0>"}.get(variant, "?")
+
+
+def measured_traffic(workload, kname):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None if there is none for this kernel
+    or its sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_apply_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        from paper_1902_08112_amd.profiling import sources_sha
+        rec = json.load(open(path))
+        if rec.get("kernel") != kname or rec.get("sources_sha") != sources_sha(rec.get("sources", [])):
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,7 +78,7 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=32)
     return ap.parse_args()
 
 
@@ -219,25 +253,34 @@ def main():
             reps.append(rep.as_dict())
         return reps
 
+    def timed(k, prec):
+        # the FP64 steps also record the duration of every finest-level FP64 Jacobian cell
+        # kernel launch with HIP events on the launch stream (the dominant kernel)
+        if prec == pff.PF_F64:
+            S.set_kernel_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = run_steps(k, prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        kt = None
+        if prec == pff.PF_F64:
+            S.set_kernel_timing(False)
+            kt = S.kernel_timing()
+        return dt, reps, kt
+
     base_prec = pff.PF_F32 if s.get("vcycle") == "f32" else pff.PF_F64
     other_prec = pff.PF_F64 if base_prec == pff.PF_F32 else pff.PF_F32
     # one step sets the linearization point; the autotuner then picks the cell-loop shape per level
     run_steps(1, base_prec)
     tuning = S.autotune(reps=10) if not a.no_tune else None
     run_steps(a.warmup, base_prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = run_steps(a.steps, base_prec)
-    torch.cuda.synchronize()
-    t_base = (time.perf_counter() - t0) / a.steps
+    t_base, reps, kt_base = timed(a.steps, base_prec)
     run_steps(a.warmup, other_prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps_o = run_steps(a.steps, other_prec)
-    torch.cuda.synchronize()
-    t_other = (time.perf_counter() - t0) / a.steps
+    t_other, reps_o, kt_other = timed(a.steps, other_prec)
     t64, t32 = (t_base, t_other) if base_prec == pff.PF_F64 else (t_other, t_base)
     r64, r32 = (reps, reps_o) if base_prec == pff.PF_F64 else (reps_o, reps)
+    kt = kt_base if base_prec == pff.PF_F64 else kt_other   # (count, mean, min, max) in s
 
     # dominant kernel: FP64 Jacobian apply on the finest level (linearization of the last step)
     x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n_vec)).cuda()
@@ -268,13 +311,26 @@ def main():
     n_cells = int(info.n_active_cells)
     flops = FLOP_PER_CELL[(s["dim"], s["degree"])] * n_cells
     bytes_ = BYTES_PER_DOF_F64[s["dim"]] * n_dofs
-    ach_tf = flops / t_apply / 1e12
+    # achieved: algorithmic flops per launch / mean duration of the launches in the timed region
+    k_count, k_mean, k_min, k_max = kt
+    t_kernel = k_mean if k_count > 0 else t_apply
+    ach_tf = flops / t_kernel / 1e12
+    variant = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 0)[0]
+    kname = kernel_name(s["dim"], s["degree"], variant)
     roof = {"bound": "alu", "achieved": round(ach_tf, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach_tf / FP64_PEAK_TFLOPS, 5), "traffic": None,
-            "kernel": "FP64 Jacobian apply, finest level", "flop_per_launch": flops, "bytes_per_launch": bytes_,
-            "hbm_achieved_GBs": round(bytes_ / t_apply / 1e9, 2),
-            "hbm_frac": round(bytes_ / t_apply / 1e9 / HBM_PEAK_GBS, 5),
-            "apply_s": t_apply, "apply_f32_s": t_apply32}
+            "frac": round(ach_tf / FP64_PEAK_TFLOPS, 5), "traffic": measured_traffic(a.workload, kname),
+            "kernel": kname, "launches_timed": k_count, "kernel_s_mean": t_kernel, "kernel_s_min": k_min,
+            "kernel_s_max": k_max, "flop_per_launch": flops, "bytes_per_launch": bytes_,
+            "hbm_achieved_GBs": round(bytes_ / t_kernel / 1e9, 2),
+            "hbm_frac": round(bytes_ / t_kernel / 1e9 / HBM_PEAK_GBS, 5),
+            "apply_call_s": t_apply, "apply_call_f32_s": t_apply32}
+    # plain device copy of a known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
+    # in rocprofv3 --pmc runs of this same command (not timed, not part of the result)
+    src = torch.rand(n_vec, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
     out = {
         "metric": METRIC,

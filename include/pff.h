@@ -232,6 +232,17 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
  * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
  * Q2 levels have one kernel and are skipped. */
 pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
+/* HIP-event timing of the finest-level FP64 Jacobian cell kernel (the dominant
+ * kernel of a Newton step).  enable = 1 clears the record and, from then on,
+ * brackets every such launch (pf_jacobian_apply on the finest level, the
+ * FGMRES operator applies and true residuals of pf_newton_step) with two
+ * events on the launch stream; the Pi_C start of y is outside the bracket.
+ * At most 1024 launches are recorded per period.  Timing adds two event
+ * records per launch; enable = 0 stops recording and keeps the record. */
+pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable);
+/* Number of recorded launches and their mean / min / max duration in seconds
+ * (waits for the last recorded launch).  count = 0 gives zeros. */
+pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s);
 /* Read / force the choice of one (level, prec, mode); variant -1 = size heuristic,
  * zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */
 pf_status pf_get_tuning(pf_ctx* ctx, int level, int prec, int mode, int* variant, int* zc);

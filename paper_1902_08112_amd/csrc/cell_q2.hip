@@ -35,14 +35,16 @@ struct Q2Tab {
   T cbx[3], cdx[3];          // B[q][tx], D[q][tx]
   T cby[3], cdy[3];          // B[q][ty], D[q][ty]
   T wx, wy, W[3];            // Gauss weights
-  __device__ Q2Tab(int tx, int ty) {
+  // squared: the tables of B^2 and D^2 (the diagonal of the element matrices)
+  __device__ Q2Tab(int tx, int ty, bool squared = false) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       W[q] = T(B1<2>::wt(q));
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        B[q][a] = T(B1<2>::val(a, B1<2>::pt(q)));
-        D[q][a] = T(B1<2>::der(a, B1<2>::pt(q)));
+        const double b = B1<2>::val(a, B1<2>::pt(q)), d = B1<2>::der(a, B1<2>::pt(q));
+        B[q][a] = T(squared ? b * b : b);
+        D[q][a] = T(squared ? d * d : d);
       }
     }
 #pragma unroll
@@ -168,7 +170,9 @@ __device__ __forceinline__ void q2_backward(Q2Lds<T>& L, const Q2Tab<T>& k, int 
 }  // namespace
 
 // MODE: MODE_APPLY / MODE_BLOCK (masked direction, y pre-set to Pi_C x), MODE_RAW
-// (unmasked G x), MODE_RESID (-A(U); x unused).
+// (unmasked G x), MODE_RESID (-A(U); x unused), MODE_DIAG (diag G, every row; x unused).
+// The diagonal entry of node a is a sum over Gauss points of products of squared 1D
+// basis values / derivatives, i.e. the backward contraction with the tables B^2, D^2.
 template <typename T, int MODE>
 __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict__ x, const T* __restrict__ U,
                                               const T* __restrict__ phit, const uint8_t* __restrict__ mask,
@@ -176,6 +180,7 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
   constexpr bool kMasked = (MODE == MODE_APPLY || MODE == MODE_BLOCK);
   constexpr bool kCouple = (MODE == MODE_APPLY || MODE == MODE_RAW);
   constexpr bool kResid = (MODE == MODE_RESID);
+  constexpr bool kDiag = (MODE == MODE_DIAG);
   __shared__ Q2Lds<T> L;
   const int tid = threadIdx.x;
   const int cs = tid / 9;  // 0 .. kQ2Cells (the last slot is the idle lane's)
@@ -264,6 +269,38 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
       rsu[qz][5] = -gdeg[qz] * s12;
       rf[qz] = -((T(1) - kap) * ph * Es + T(2) * ph * pres * tr - gce * (T(1) - ph));
     }
+  }
+
+  if constexpr (kDiag) {
+    const Q2Tab<T> k2(tx, ty, true);
+    T cv[3], cg[3][3], out[3];
+    // u_c rows: gdeg (mu |grad N_a|^2 + (mu + lambda) (d_c N_a)^2)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int qz = 0; qz < 3; ++qz) {
+          cv[qz] = T(0);
+          cg[j][qz] = jxw[qz] * gdeg[qz] * (j == c ? T(2) * mu + lam : mu) * ih[j] * ih[j];
+        }
+      q2_backward<T, false>(L, k2, cs, tx, ty, cv, cg, out);
+      if (active)
+#pragma unroll
+        for (int az = 0; az < 3; ++az) atomicAdd(&y[c * nn + gi[az]], out[az]);
+    }
+    // phase-field row: cphi N_a^2 + G_c eps |grad N_a|^2
+#pragma unroll
+    for (int qz = 0; qz < 3; ++qz) {
+      cv[qz] = jxw[qz] * cphi[qz];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) cg[j][qz] = jxw[qz] * gcx * ih[j] * ih[j];
+    }
+    q2_backward<T, true>(L, k2, cs, tx, ty, cv, cg, out);
+    if (active)
+#pragma unroll
+      for (int az = 0; az < 3; ++az) atomicAdd(&y[3 * nn + gi[az]], out[az]);
+    return;
   }
 
   // displacement rows: test-gradient coefficients per component
@@ -359,7 +396,8 @@ pf_status launch_cell_q2(const Geom& g, const CellParams& cp, int mode, const T*
   *handled = false;
   if (g.d != 3 || g.p != 2) return PF_OK;
   const bool fp64 = sizeof(T) == 8;
-  if (!(mode == MODE_APPLY || mode == MODE_BLOCK || (fp64 && (mode == MODE_RAW || mode == MODE_RESID)))) return PF_OK;
+  if (!(mode == MODE_APPLY || mode == MODE_BLOCK || (fp64 && (mode == MODE_RAW || mode == MODE_RESID || mode == MODE_DIAG))))
+    return PF_OK;
   *handled = true;
   const int64_t nb = (g.n_cells + kQ2Cells - 1) / kQ2Cells;
   if (nb == 0) return PF_OK;
@@ -372,6 +410,9 @@ pf_status launch_cell_q2(const Geom& g, const CellParams& cp, int mode, const T*
       break;
     case MODE_RAW:
       k_q2_3d<T, MODE_RAW><<<nb, 64, 0, s>>>(cp, x, U, phit, mask, y);
+      break;
+    case MODE_DIAG:
+      k_q2_3d<T, MODE_DIAG><<<nb, 64, 0, s>>>(cp, x, U, phit, mask, y);
       break;
     default:
       k_q2_3d<T, MODE_RESID><<<nb, 64, 0, s>>>(cp, x, U, phit, mask, y);

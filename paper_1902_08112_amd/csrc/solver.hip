@@ -130,6 +130,7 @@ using namespace pff;
 constexpr size_t kPartStride = 2 * kRedMaxBlocks + 256;
 // FGMRES scalars per Arnoldi step, device dscal[0 .. kHostScal): h1 at 0, h2 at 256, |w|^2 at 512
 constexpr int kHostScal = 520;
+constexpr int kKernelTimerMax = 1024;  // timed launches kept per pf_set_kernel_timing period
 
 struct LevelBuf {
   Geom g;
@@ -144,7 +145,7 @@ struct LevelBuf {
   // cell-loop choice per [precision][mode APPLY/BLOCK]: variant and marching chunk (-1: heuristic)
   int variant[2][2] = {{-1, -1}, {-1, -1}};
   int zc[2][2] = {{-1, -1}, {-1, -1}};
-  double tune_us[2][2][12] = {};  // measured candidates (autotune report)
+  double tune_us[2][2][16] = {};  // measured candidates (autotune report)
 };
 
 struct pf_ctx {
@@ -168,6 +169,10 @@ struct pf_ctx {
   hipEvent_t fork_ev = nullptr;
   double* part_lev = nullptr;
   double* host_scal = nullptr;  // pinned host copy of the FGMRES scalars (kHostScal doubles)
+  // optional HIP-event timing of the finest-level FP64 Jacobian cell kernel (pf_set_kernel_timing)
+  bool ktime_on = false;
+  int ktime_n = 0;
+  std::vector<hipEvent_t> ktime_ev;  // pairs (start, end), kKernelTimerMax of them
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
@@ -189,6 +194,7 @@ struct pf_ctx {
     for (hipEvent_t e : aux_ev) hipEventDestroy(e);
     if (fork_ev) hipEventDestroy(fork_ev);
     if (host_scal) hipHostFree(host_scal);
+    for (hipEvent_t e : ktime_ev) hipEventDestroy(e);
   }
   bool has_extra = false, has_lin = false;
   size_t ws_bytes = 0;
@@ -413,6 +419,17 @@ pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void*
                       bool y_preset = false) {
   LevelBuf& b = c->lev[l];
   const CellParams cp = level_params(c, l, prec, mode);
+  if (c->ktime_on && prec == PF_F64 && mode == MODE_APPLY && l == (int)c->lev.size() - 1 &&
+      c->ktime_n < kKernelTimerMax) {
+    // the Pi_C start (when needed) outside, the cell kernel alone between the two events
+    if (!y_preset && !q1_tiled_handles(b.g, mode, cp.variant))
+      PFF_TRY(vec_init_constrained<double>((double*)y, (const double*)x, b.mask, b.g.n_nodes, b.g.d, s));
+    hipEvent_t* ev = &c->ktime_ev[2 * c->ktime_n++];
+    PFF_HIP(hipEventRecord(ev[0], s));
+    PFF_TRY(launch_cell<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s));
+    PFF_HIP(hipEventRecord(ev[1], s));
+    return PF_OK;
+  }
   if (prec == PF_F64)
     return apply_op<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s, y_preset);
   return apply_op<float>(b.g, cp, mode, (const float*)x, b.U32, b.phit32, b.mask, (float*)y, s, y_preset);
@@ -1005,6 +1022,40 @@ pf_status pf_jacobian_apply(pf_ctx* ctx, int level, int prec, const void* d_x, v
   return apply_entry(ctx, level, prec, MODE_APPLY, d_x, d_y, stream);
 }
 
+pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable) {
+  NEED_CTX();
+  if (enable && ctx->ktime_ev.empty()) {
+    ctx->ktime_ev.resize(2 * kKernelTimerMax, nullptr);
+    for (auto& e : ctx->ktime_ev) PFF_HIP(hipEventCreate(&e));
+  }
+  ctx->ktime_on = enable != 0;
+  if (enable) ctx->ktime_n = 0;
+  return PF_OK;
+}
+
+pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s) {
+  NEED_CTX();
+  if (!count || !avg_s || !min_s || !max_s) {
+    set_error("count, avg_s, min_s and max_s must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  double sum = 0.0, lo = 0.0, hi = 0.0;
+  for (int i = 0; i < ctx->ktime_n; ++i) {
+    PFF_HIP(hipEventSynchronize(ctx->ktime_ev[2 * i + 1]));
+    float ms = 0.f;
+    PFF_HIP(hipEventElapsedTime(&ms, ctx->ktime_ev[2 * i], ctx->ktime_ev[2 * i + 1]));
+    const double t = 1e-3 * ms;
+    sum += t;
+    lo = i ? std::min(lo, t) : t;
+    hi = i ? std::max(hi, t) : t;
+  }
+  *count = ctx->ktime_n;
+  *avg_s = ctx->ktime_n ? sum / ctx->ktime_n : 0.0;
+  *min_s = lo;
+  *max_s = hi;
+  return PF_OK;
+}
+
 pf_status pf_block_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream) {
   return apply_entry(ctx, level, prec, MODE_BLOCK, d_x, d_y, stream);
 }
@@ -1224,8 +1275,11 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
 
 // ---------------------------------------------------------------------------------- autotuner
 // Candidates of the Q1 cell loop: (variant, chunk).  Variants 1 (16x4 tiles) and 3 (LDS bricks) are 3D only.
-static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {1, 4}, {1, 8}, {1, 16}};
-static const int kNCand = 9;
+// Small chunks suit levels that barely fill the chip, long ones (fewer recomputed halo
+// layers) the large levels.
+static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {0, 32}, {0, 64},
+                               {1, 4}, {1, 8}, {1, 16}, {1, 32}};
+static const int kNCand = 12;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];

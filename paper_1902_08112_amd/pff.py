@@ -84,6 +84,8 @@ SIGNATURES = {
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
+    "pf_set_kernel_timing": (I, [VP, I]),
+    "pf_get_kernel_timing": (I, [VP, C.POINTER(I), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pf_batch_workspace_size": (I, [C.POINTER(Mesh), I, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "pf_batch_setup": (I, [C.POINTER(Mesh), C.POINTER(D), I, C.POINTER(Options), VP, C.c_size_t, VP,
                            C.POINTER(VP)]),
@@ -410,6 +412,17 @@ class Solver:
 
     def set_graphs(self, enable):
         _check(lib().pf_set_graphs(self.ctx, 1 if enable else 0), "pf_set_graphs")
+
+    def set_kernel_timing(self, enable):
+        """Bracket every finest-level FP64 Jacobian cell kernel with HIP events (see pff.h)."""
+        _check(lib().pf_set_kernel_timing(self.ctx, 1 if enable else 0), "pf_set_kernel_timing")
+
+    def kernel_timing(self):
+        """(count, mean_s, min_s, max_s) of the launches recorded since timing was enabled."""
+        n, a, lo, hi = I(0), D(0), D(0), D(0)
+        _check(lib().pf_get_kernel_timing(self.ctx, C.byref(n), C.byref(a), C.byref(lo), C.byref(hi)),
+               "pf_get_kernel_timing")
+        return n.value, a.value, lo.value, hi.value
 
     # autotuner ---------------------------------------------------------------
     def tuning_key(self):
