@@ -19,24 +19,15 @@ namespace {
 
 constexpr int kQ2Cells = 7;  // cells per 64-thread workgroup (63 active threads)
 
-template <typename T>
-__device__ __forceinline__ T sel3(int i, T a, T b, T c) {
-  return i == 0 ? a : (i == 1 ? b : c);
-}
-
-// 1D tables of a thread: B[q][a] = L_a(t_q), D[q][a] = L_a'(t_q) on the Gauss points t_q.
-// The lane-dependent rows / columns are selected among compile-time constants (no
-// dynamically indexed private arrays).
+// 1D tables on the Gauss points t_q: B[q][a] = L_a(t_q), D[q][a] = L_a'(t_q), weights W[q].
+// Entries with compile-time indices fold into immediates; the lane-dependent rows and
+// columns are read from a copy in LDS (one table per workgroup, broadcast reads), which
+// keeps them out of the register file.
 template <typename T>
 struct Q2Tab {
-  T B[3][3], D[3][3];        // full tables (compile-time indices only)
-  T rbx[3], rdx[3];          // B[tx][a], D[tx][a]
-  T rby[3], rdy[3];          // B[ty][a], D[ty][a]
-  T cbx[3], cdx[3];          // B[q][tx], D[q][tx]
-  T cby[3], cdy[3];          // B[q][ty], D[q][ty]
-  T wx, wy, W[3];            // Gauss weights
-  // squared: the tables of B^2 and D^2 (the diagonal of the element matrices)
-  __device__ Q2Tab(int tx, int ty, bool squared = false) {
+  T B[3][3], D[3][3], W[3];
+  // squared: B^2 and D^2 (the diagonal of the element matrices)
+  __device__ explicit Q2Tab(bool squared = false) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       W[q] = T(B1<2>::wt(q));
@@ -47,27 +38,29 @@ struct Q2Tab {
         D[q][a] = T(squared ? d * d : d);
       }
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      rbx[a] = sel3(tx, B[0][a], B[1][a], B[2][a]);
-      rdx[a] = sel3(tx, D[0][a], D[1][a], D[2][a]);
-      rby[a] = sel3(ty, B[0][a], B[1][a], B[2][a]);
-      rdy[a] = sel3(ty, D[0][a], D[1][a], D[2][a]);
-      cbx[a] = sel3(tx, B[a][0], B[a][1], B[a][2]);
-      cdx[a] = sel3(tx, D[a][0], D[a][1], D[a][2]);
-      cby[a] = sel3(ty, B[a][0], B[a][1], B[a][2]);
-      cdy[a] = sel3(ty, D[a][0], D[a][1], D[a][2]);
-    }
-    wx = sel3(tx, W[0], W[1], W[2]);
-    wy = sel3(ty, W[0], W[1], W[2]);
   }
 };
+
+// the LDS copy of the (squared) tables, written by the first nine threads
+template <typename T>
+__device__ __forceinline__ void q2_fill_tables(T (&tb)[3][3], T (&td)[3][3], int tid, bool squared) {
+  if (tid < 9) {
+    const int q = tid / 3, a = tid % 3;
+    const double t = B1<2>::pt(q), b = B1<2>::val(a, t), d = B1<2>::der(a, t);
+    tb[q][a] = T(squared ? b * b : b);
+    td[q][a] = T(squared ? d * d : d);
+  }
+}
 
 // per-workgroup exchange buffers: [buffer][cell slot][az][ay][ax]; slot kQ2Cells belongs to
 // the idle lane 63, which runs the same code (barriers) on its own data
 template <typename T>
 struct Q2Lds {
+  T tb[3][3], td[3][3];  // B and D (or their squares for the diagonal)
   T s[3][kQ2Cells + 1][3][3][3];
+  // per thread and Gauss point: g(phi~) JxW, the phase-field coefficient, the coupling tensor
+  // (6); written and read by the same thread only (parked here to bound live registers)
+  T q[kQ2Cells + 1][9][3][8];
 };
 
 // Forward contraction of one scalar field.  col[az] = f(tx, ty, az).  Output at the
@@ -84,8 +77,8 @@ __device__ __forceinline__ void q2_forward(Q2Lds<T>& L, const Q2Tab<T>& k, int c
   T bx[3], dx[3];
 #pragma unroll
   for (int az = 0; az < 3; ++az) {
-    bx[az] = k.rbx[0] * S0[az][ty][0] + k.rbx[1] * S0[az][ty][1] + k.rbx[2] * S0[az][ty][2];
-    if (GRAD) dx[az] = k.rdx[0] * S0[az][ty][0] + k.rdx[1] * S0[az][ty][1] + k.rdx[2] * S0[az][ty][2];
+    bx[az] = L.tb[tx][0] * S0[az][ty][0] + L.tb[tx][1] * S0[az][ty][1] + L.tb[tx][2] * S0[az][ty][2];
+    if (GRAD) dx[az] = L.td[tx][0] * S0[az][ty][0] + L.td[tx][1] * S0[az][ty][1] + L.td[tx][2] * S0[az][ty][2];
   }
   __syncthreads();
 #pragma unroll
@@ -97,10 +90,10 @@ __device__ __forceinline__ void q2_forward(Q2Lds<T>& L, const Q2Tab<T>& k, int c
   T bb[3], bd[3], db[3];
 #pragma unroll
   for (int az = 0; az < 3; ++az) {
-    bb[az] = k.rby[0] * S0[az][0][tx] + k.rby[1] * S0[az][1][tx] + k.rby[2] * S0[az][2][tx];
+    bb[az] = L.tb[ty][0] * S0[az][0][tx] + L.tb[ty][1] * S0[az][1][tx] + L.tb[ty][2] * S0[az][2][tx];
     if (GRAD) {
-      bd[az] = k.rdy[0] * S0[az][0][tx] + k.rdy[1] * S0[az][1][tx] + k.rdy[2] * S0[az][2][tx];
-      db[az] = k.rby[0] * S1[az][0][tx] + k.rby[1] * S1[az][1][tx] + k.rby[2] * S1[az][2][tx];
+      bd[az] = L.td[ty][0] * S0[az][0][tx] + L.td[ty][1] * S0[az][1][tx] + L.td[ty][2] * S0[az][2][tx];
+      db[az] = L.tb[ty][0] * S1[az][0][tx] + L.tb[ty][1] * S1[az][1][tx] + L.tb[ty][2] * S1[az][2][tx];
     }
   }
   __syncthreads();
@@ -149,9 +142,9 @@ __device__ __forceinline__ void q2_backward(Q2Lds<T>& L, const Q2Tab<T>& k, int 
   T y0[3], yx[3];
 #pragma unroll
   for (int az = 0; az < 3; ++az) {
-    y0[az] = k.cby[0] * S0[az][0][tx] + k.cby[1] * S0[az][1][tx] + k.cby[2] * S0[az][2][tx] +
-             k.cdy[0] * S1[az][0][tx] + k.cdy[1] * S1[az][1][tx] + k.cdy[2] * S1[az][2][tx];
-    yx[az] = k.cby[0] * S2[az][0][tx] + k.cby[1] * S2[az][1][tx] + k.cby[2] * S2[az][2][tx];
+    y0[az] = L.tb[0][ty] * S0[az][0][tx] + L.tb[1][ty] * S0[az][1][tx] + L.tb[2][ty] * S0[az][2][tx] +
+             L.td[0][ty] * S1[az][0][tx] + L.td[1][ty] * S1[az][1][tx] + L.td[2][ty] * S1[az][2][tx];
+    yx[az] = L.tb[0][ty] * S2[az][0][tx] + L.tb[1][ty] * S2[az][1][tx] + L.tb[2][ty] * S2[az][2][tx];
   }
   __syncthreads();
 #pragma unroll
@@ -162,8 +155,8 @@ __device__ __forceinline__ void q2_backward(Q2Lds<T>& L, const Q2Tab<T>& k, int 
   __syncthreads();
 #pragma unroll
   for (int az = 0; az < 3; ++az)
-    out[az] = k.cbx[0] * S0[az][ty][0] + k.cbx[1] * S0[az][ty][1] + k.cbx[2] * S0[az][ty][2] +
-              k.cdx[0] * S1[az][ty][0] + k.cdx[1] * S1[az][ty][1] + k.cdx[2] * S1[az][ty][2];
+    out[az] = L.tb[0][tx] * S0[az][ty][0] + L.tb[1][tx] * S0[az][ty][1] + L.tb[2][tx] * S0[az][ty][2] +
+              L.td[0][tx] * S1[az][ty][0] + L.td[1][tx] * S1[az][ty][1] + L.td[2][tx] * S1[az][ty][2];
   __syncthreads();
 }
 
@@ -174,7 +167,7 @@ __device__ __forceinline__ void q2_backward(Q2Lds<T>& L, const Q2Tab<T>& k, int 
 // The diagonal entry of node a is a sum over Gauss points of products of squared 1D
 // basis values / derivatives, i.e. the backward contraction with the tables B^2, D^2.
 template <typename T, int MODE>
-__global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict__ x, const T* __restrict__ U,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_q2_3d(CellParams cp, const T* __restrict__ x, const T* __restrict__ U,
                                               const T* __restrict__ phit, const uint8_t* __restrict__ mask,
                                               T* __restrict__ y) {
   constexpr bool kMasked = (MODE == MODE_APPLY || MODE == MODE_BLOCK);
@@ -185,7 +178,9 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
   const int tid = threadIdx.x;
   const int cs = tid / 9;  // 0 .. kQ2Cells (the last slot is the idle lane's)
   const int tx = (tid % 9) % 3, ty = (tid % 9) / 3;
-  const Q2Tab<T> k(tx, ty);
+  const Q2Tab<T> k;
+  q2_fill_tables(L.tb, L.td, tid, false);
+  __syncthreads();
   const int64_t cid = (int64_t)blockIdx.x * kQ2Cells + tid / 9;
   bool active = tid < 9 * kQ2Cells && cid < cp.n_cells;
   int cx = 0, cy = 0, cz = 0;
@@ -209,7 +204,7 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
   const T gce = T(cp.gc_over_eps), gcx = T(cp.gc_eps);
   T jxw[3];
 #pragma unroll
-  for (int qz = 0; qz < 3; ++qz) jxw[qz] = T(cp.vol) * k.wx * k.wy * k.W[qz];
+  for (int qz = 0; qz < 3; ++qz) jxw[qz] = T(cp.vol * B1<2>::wt(tx) * B1<2>::wt(ty)) * k.W[qz];
 
   // linearization point at the Gauss points: g(phi~), and the phase-field coefficients
   T col[3], tmp[3][3];
@@ -272,7 +267,10 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
   }
 
   if constexpr (kDiag) {
-    const Q2Tab<T> k2(tx, ty, true);
+    const Q2Tab<T> k2(true);
+    __syncthreads();  // every read of the plain tables is done
+    q2_fill_tables(L.tb, L.td, tid, true);
+    __syncthreads();
     T cv[3], cg[3][3], out[3];
     // u_c rows: gdeg (mu |grad N_a|^2 + (mu + lambda) (d_c N_a)^2)
 #pragma unroll
@@ -312,7 +310,20 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
 #pragma unroll
       for (int m = 0; m < 6; ++m) tau[qz][m] = rsu[qz][m] * jxw[qz];
   } else {
-    T gd[3][3][3];
+    // park the linearization data of the thread's Gauss points; tau and the coupling term
+    // accumulate one direction component at a time (tau is linear in grad du)
+    T (&Q)[3][8] = L.q[cs][tid % 9];
+#pragma unroll
+    for (int qz = 0; qz < 3; ++qz) {
+      Q[qz][0] = gdeg[qz] * jxw[qz];
+      Q[qz][1] = cphi[qz];
+      if (kCouple)
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Q[qz][2 + m] = Ksym[qz][m];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) tau[qz][m] = T(0);
+    }
+    constexpr int kSym[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -320,26 +331,26 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
         T v = active ? x[c * nn + gi[az]] : T(0);
         col[az] = (mk[az] & (1 << c)) ? T(0) : v;
       }
-      T v[3];
-      q2_forward<T, true>(L, k, cs, tx, ty, col, ih, v, gd[c]);
-    }
+      T v[3], gdc[3][3];
+      q2_forward<T, true>(L, k, cs, tx, ty, col, ih, v, gdc);
 #pragma unroll
-    for (int qz = 0; qz < 3; ++qz) {
-      const T d00 = gd[0][0][qz], d11 = gd[1][1][qz], d22 = gd[2][2][qz];
-      const T d01 = T(0.5) * (gd[0][1][qz] + gd[1][0][qz]);
-      const T d02 = T(0.5) * (gd[0][2][qz] + gd[2][0][qz]);
-      const T d12 = T(0.5) * (gd[1][2][qz] + gd[2][1][qz]);
-      const T trd = d00 + d11 + d22;
-      const T w = gdeg[qz] * jxw[qz];
-      tau[qz][0] = w * (T(2) * mu * d00 + lam * trd);
-      tau[qz][1] = w * (T(2) * mu * d11 + lam * trd);
-      tau[qz][2] = w * (T(2) * mu * d22 + lam * trd);
-      tau[qz][3] = w * T(2) * mu * d01;
-      tau[qz][4] = w * T(2) * mu * d02;
-      tau[qz][5] = w * T(2) * mu * d12;
-      if (kCouple)
-        fcpl[qz] = Ksym[qz][0] * d00 + Ksym[qz][1] * d11 + Ksym[qz][2] * d22 +
-                   T(2) * (Ksym[qz][3] * d01 + Ksym[qz][4] * d02 + Ksym[qz][5] * d12);
+      for (int qz = 0; qz < 3; ++qz) {
+        const T w = Q[qz][0];
+        const T tl = w * lam * gdc[c][qz];
+        tau[qz][0] += tl;
+        tau[qz][1] += tl;
+        tau[qz][2] += tl;
+        tau[qz][c] += w * T(2) * mu * gdc[c][qz];
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (j != c) tau[qz][kSym[c][j]] += w * mu * gdc[j][qz];
+        if (kCouple) {
+          T f = T(0);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) f += Q[qz][2 + kSym[c][j]] * gdc[j][qz];
+          fcpl[qz] += f;
+        }
+      }
     }
   }
   // the symmetric tau row of component c: (c, 0), (c, 1), (c, 2)
@@ -375,9 +386,10 @@ __global__ __launch_bounds__(64) void k_q2_3d(CellParams cp, const T* __restrict
     }
     T dpv[3], gdp[3][3];
     q2_forward<T, true>(L, k, cs, tx, ty, col, ih, dpv, gdp);
+    const T (&Q)[3][8] = L.q[cs][tid % 9];
 #pragma unroll
     for (int qz = 0; qz < 3; ++qz) {
-      cv[qz] = (cphi[qz] * dpv[qz] + fcpl[qz]) * jxw[qz];
+      cv[qz] = (Q[qz][1] * dpv[qz] + fcpl[qz]) * jxw[qz];
 #pragma unroll
       for (int j = 0; j < 3; ++j) cg[j][qz] = gcx * gdp[j][qz] * jxw[qz] * ih[j];
     }
