@@ -122,6 +122,7 @@ class Options:
     gmres_restart: int = 50
     gmres_max_iter: int = 500
     gmres_rtol: float = 1e-8
+    gmres_atol: float = 0.0          # absolute floor: stop at max(rtol ||R~||, atol)
     pdas_c: float = 100.0
     eig_seed: int = 12345
 

@@ -52,7 +52,8 @@ def newton_step(hier, U, U_old, phit, solver="fgmres", eig_bounds=None):
     else:
         hier.set_linearization(U, phit, active, eig_bounds=eig_bounds)
         dU, info = fgmres(lambda x: Gt @ x, hier.vcycle, Rt, lift.copy(),
-                          rtol=o.gmres_rtol, restart=o.gmres_restart, max_iter=o.gmres_max_iter)
+                          rtol=o.gmres_rtol, restart=o.gmres_restart, max_iter=o.gmres_max_iter,
+                          atol=o.gmres_atol)
     res = float(np.linalg.norm(Rt - Gt @ dU))
     return dict(U=U + dU, dU=dU, active=active, v=v, R=R, Rt=Rt, constrained=cons,
                 n_active=int(active.sum()), rel_res=res / float(np.linalg.norm(Rt)), info=info)
