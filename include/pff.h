@@ -90,9 +90,11 @@ typedef struct pf_options {
   double coarse_lo_factor; /* coarse range lower end = factor * lam_min */
   int gmres_restart;       /* FGMRES restart length m (workspace grows with m) */
   int gmres_max_iter;      /* total FGMRES iteration cap */
-  double gmres_rtol;       /* stop when ||R~ - G~ dU|| <= rtol ||R~|| (true residual) */
+  double gmres_rtol;       /* stop when ||R~ - G~ dU|| <= max(rtol ||R~||, atol) (true residual) */
   double pdas_c;           /* active-set constant c */
   uint64_t eig_seed;       /* SplitMix64 seed of the eigenvalue start vectors */
+  double gmres_atol;       /* absolute floor of the FGMRES stop (default 0; the inexact solves of
+                              Sec. 5 use rtol 1e-4 with a small floor) */
 } pf_options;
 
 typedef struct pf_newton_report {
@@ -106,6 +108,16 @@ typedef struct pf_newton_report {
   double t_solve_s;         /* wall time of step 5 (FGMRES) */
   double t_total_s;
 } pf_newton_report;
+
+typedef struct pf_pdas_report {
+  int iterations;           /* linear solves done (Newton corrections) */
+  int converged;            /* 1 if A_k = A_{k-1} and ||R~_k|| <= tol_as was reached */
+  int gmres_iters_total;    /* FGMRES iterations summed over the corrections */
+  int64_t n_active;         /* |A_k| of the last iteration */
+  int64_t n_changed;        /* |A_k xor A_{k-1}| of the last iteration (-1 if k = 0) */
+  double residual_norm;     /* ||R~_k|| of the last iteration (absolute, FP64) */
+  double t_total_s;
+} pf_pdas_report;
 
 typedef struct pf_level_info {
   int n_cells[3];
@@ -215,6 +227,30 @@ pf_status pf_vcycle(pf_ctx* ctx, int prec, const double* d_r, double* d_z, void*
  * PF_ERR_NONFINITE if the residual is not finite (U unchanged). */
 pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde,
                          pf_newton_report* rep, void* stream);
+
+/* The primal-dual active-set loop (Algorithm 1 of Sec. 3.1 repeated): for
+ * k = 0, 1, ... compute R_k, A_k and R~_k; stop when k > 0, A_k = A_{k-1}
+ * and ||R~_k|| <= tol_as (absolute, the eps_as = 1e-10 of Sec. 5), else solve
+ * and update as pf_newton_step.  At most max_iter corrections (>= 1).  The
+ * check comes before the solve, so a converged iteration costs only the
+ * residual.  d_U (in/out), d_U_old, d_phi_tilde as in pf_newton_step.
+ * Synchronizes.  Returns PF_ERR_NOT_CONVERGED if max_iter corrections do not
+ * converge or an FGMRES solve stops at gmres_max_iter (report filled, U holds
+ * the last iterate), PF_ERR_NONFINITE on a non-finite residual. */
+pf_status pf_pdas_solve(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde, int max_iter,
+                        double tol_as, pf_pdas_report* rep, void* stream);
+
+/* Time-lagged extrapolation of the phase field for the displacement equation
+ * (Sec. 2.3): d_out = phi_1 + theta (phi_1 - phi_2) on the finest level's
+ * nodes (n_nodes entries each), with phi_1 = phi^{n-1}, phi_2 = phi^{n-2} and
+ * theta = dt_n / dt_{n-1} (1 for a constant step; linear in time).  d_out may
+ * alias neither input.  Hole nodes are copied from phi_1.  Asynchronous. */
+pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi_2, double theta, double* d_out,
+                         void* stream);
+
+/* Set the crack pressure p of the loading (Sec. 5.1: p(t) = 1e3 t); finite.
+ * Takes effect at the next operator, residual or set-up call. */
+pf_status pf_set_pressure(pf_ctx* ctx, double pressure);
 
 /* Level sizes. */
 pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);

@@ -1029,7 +1029,7 @@ pf_status bfgmres(pf_batch* c, const double* b, double* x, int vprec, std::vecto
   std::vector<double> tol(B);
   for (int i = 0; i < B; ++i) {
     bnorm[i] = std::sqrt(hb[i]);
-    tol[i] = c->opt.gmres_rtol * bnorm[i];
+    tol[i] = std::max(c->opt.gmres_rtol * bnorm[i], c->opt.gmres_atol);
   }
   auto true_res = [&](std::vector<double>& beta) -> pf_status {
     PFF_TRY(bapply(c, L - 1, PF_F64, MODE_APPLY, x, c->t, s));
@@ -1416,7 +1416,7 @@ pf_status pf_batch_newton_step(pf_batch* bt, double* d_U, const double* d_U_old,
   const double t3 = now();
   bool all = true;
   for (int b = 0; b < B; ++b) {
-    const bool conv = rel[b] <= bt->opt.gmres_rtol;
+    const bool conv = rel[b] * bn[b] <= std::max(bt->opt.gmres_rtol * bn[b], bt->opt.gmres_atol);
     all = all && conv;
     if (reps) {
       pf_newton_report& r = reps[b];

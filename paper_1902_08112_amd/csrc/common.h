@@ -215,6 +215,12 @@ pf_status pdas_decide(const Geom& g, const double* R, const double* U, const dou
                       const uint8_t* base_mask, double c, uint8_t* active, double* v, hipStream_t s);
 // count of nonzero bytes (host result)
 pf_status count_bytes(const uint8_t* a, int64_t n, double* d_partials, int64_t* h_out, hipStream_t s);
+// positions where two masks differ as flags (host result)
+pf_status count_diff_bytes(const uint8_t* a, const uint8_t* b, int64_t n, double* d_partials, int64_t* h_out,
+                           hipStream_t s);
+// phi~ = phi_1 + theta (phi_1 - phi_2) on nodes; nodes whose base mask constrains phi (hole) copy phi_1
+pf_status extrapolate_phase(const double* phi_1, const double* phi_2, double theta, const uint8_t* base, int64_t n,
+                            double* out, hipStream_t s);
 // mask = base | extra | (active ? 8 : 0)
 pf_status combine_mask(const uint8_t* base, const uint8_t* extra, const uint8_t* active, uint8_t* mask, int64_t n,
                        hipStream_t s);

@@ -188,6 +188,44 @@ __global__ void k_sum1(const double* partials, int n, double* out) {
   const double b = block_sum_g(acc);
   if (threadIdx.x == 0) *out = b;
 }
+// number of positions where two byte masks differ (as flags: nonzero = set)
+__global__ void k_count_diff(const uint8_t* a, const uint8_t* b, int64_t n, double* partials) {
+  double acc = 0.0;
+  GRID_STRIDE(i, n) acc += ((a[i] != 0) != (b[i] != 0)) ? 1.0 : 0.0;
+  const double r = block_sum_g(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+pf_status count_diff_bytes(const uint8_t* a, const uint8_t* b, int64_t n, double* d_part, int64_t* h_out,
+                           hipStream_t s) {
+  int nb = (int)((n + 255) / 256);
+  if (nb > kRedMaxBlocks) nb = kRedMaxBlocks;
+  if (nb < 1) nb = 1;
+  k_count_diff<<<nb, 256, 0, s>>>(a, b, n, d_part);
+  PFF_CHECK_LAUNCH();
+  k_sum1<<<1, 256, 0, s>>>(d_part, nb, d_part + 2 * kRedMaxBlocks);
+  PFF_CHECK_LAUNCH();
+  double h = 0;
+  PFF_HIP(hipMemcpyAsync(&h, d_part + 2 * kRedMaxBlocks, sizeof(double), hipMemcpyDeviceToHost, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  *h_out = (int64_t)h;
+  return PF_OK;
+}
+
+// time-lagged extrapolation phi~ = phi_1 + theta (phi_1 - phi_2) (hole nodes: phi_1)
+__global__ void k_extrapolate(const double* phi_1, const double* phi_2, double theta, const uint8_t* base,
+                              int64_t n, double* out) {
+  GRID_STRIDE(i, n) {
+    const double a = phi_1[i];
+    out[i] = (base[i] & kMaskPhi) ? a : a + theta * (a - phi_2[i]);
+  }
+}
+pf_status extrapolate_phase(const double* phi_1, const double* phi_2, double theta, const uint8_t* base, int64_t n,
+                            double* out, hipStream_t s) {
+  k_extrapolate<<<nblk(n), 256, 0, s>>>(phi_1, phi_2, theta, base, n, out);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
 pf_status count_bytes(const uint8_t* a, int64_t n, double* d_part, int64_t* h_out, hipStream_t s) {
   int nb = (int)((n + 255) / 256);
   if (nb > kRedMaxBlocks) nb = kRedMaxBlocks;

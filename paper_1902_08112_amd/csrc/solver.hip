@@ -154,7 +154,7 @@ struct pf_ctx {
   pf_options opt;
   std::vector<LevelBuf> lev;
   double *M = nullptr, *R = nullptr, *dl = nullptr, *Rt = nullptr, *dU = nullptr, *t = nullptr;
-  uint8_t *extra = nullptr, *active = nullptr;
+  uint8_t *extra = nullptr, *active = nullptr, *prev_active = nullptr;
   double *V = nullptr, *Z = nullptr;
   double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
   EigDev* eigdev = nullptr;  // one record per level
@@ -287,6 +287,10 @@ pf_status validate_opts(const pf_options* o) {
     set_error("FGMRES settings out of range (restart in [1, 200])");
     return PF_ERR_INVALID_ARG;
   }
+  if (!std::isfinite(o->gmres_atol) || !(o->gmres_atol >= 0.0)) {
+    set_error("gmres_atol must be finite and >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
   if (!std::isfinite(o->pdas_c) || !(o->pdas_c >= 0.0)) {
     set_error("pdas_c must be finite and >= 0");
     return PF_ERR_INVALID_ARG;
@@ -358,6 +362,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* t = cv.take<double>(nd);
   uint8_t* extra = cv.take<uint8_t>(nn);
   uint8_t* active = cv.take<uint8_t>(nn);
+  uint8_t* prev_active = cv.take<uint8_t>(nn);
   double* V = cv.take<double>((size_t)(mr + 1) * nd);
   double* Z = cv.take<double>((size_t)mr * nd);
   double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
@@ -377,6 +382,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->t = t;
     c->extra = extra;
     c->active = active;
+    c->prev_active = prev_active;
     c->V = V;
     c->Z = Z;
     c->part = part;
@@ -746,7 +752,7 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
   PFF_TRY(dot_host(b, b, n, c->part, &bn2, s));
   const double bnorm = std::sqrt(bn2);
   *bnorm_out = bnorm;
-  const double tol = c->opt.gmres_rtol * bnorm;
+  const double tol = std::max(c->opt.gmres_rtol * bnorm, c->opt.gmres_atol);
   auto true_res = [&](double* beta) -> pf_status {
     PFF_TRY(level_apply(c, L, PF_F64, MODE_APPLY, x, c->t, s));
     PFF_TRY(vec_sub<double>(c->V, b, c->t, n, s));
@@ -859,6 +865,7 @@ void pf_default_options(pf_options* o) {
   o->gmres_restart = 50;
   o->gmres_max_iter = 500;
   o->gmres_rtol = 1e-8;
+  o->gmres_atol = 0.0;
   o->pdas_c = 100.0;
   o->eig_seed = 12345;
 }
@@ -1190,6 +1197,54 @@ pf_status pf_vcycle(pf_ctx* ctx, int prec, const double* d_r, double* d_z, void*
   return vcycle_any(ctx, prec, d_r, d_z, st(stream));
 }
 
+// Steps 1, 3 and 4 of Algorithm 1 at U_k: R = -A(U_k), the active set, the lift and
+// R~ = Pi_F (R - G d) + d on the finest level (no level data yet).
+pf_status newton_prepare(pf_ctx* ctx, const double* d_U, const double* d_U_old, const double* d_phi_tilde,
+                         int64_t* n_active, double* rt_norm, hipStream_t s, double* t_resid = nullptr) {
+  const int L = (int)ctx->lev.size() - 1;
+  LevelBuf& f = ctx->lev[L];
+  const Geom& g = f.g;
+  const double t0 = now_s();
+  PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RESID, nullptr, d_U, d_phi_tilde, f.mask, ctx->R, s));
+  double bad = 0;
+  PFF_TRY(count_nonfinite(ctx->R, g.n_dofs, ctx->part, &bad, s));  // synchronizes
+  if (t_resid) *t_resid = now_s() - t0;
+  if (bad > 0) {
+    set_error("non-finite residual (check U, U_old, phi_tilde)");
+    return PF_ERR_NONFINITE;
+  }
+  PFF_TRY(pdas_decide(g, ctx->R, d_U, d_U_old, ctx->M, f.base, ctx->opt.pdas_c, ctx->active, nullptr, s));
+  PFF_TRY(count_bytes(ctx->active, g.n_nodes, ctx->part, n_active, s));
+  PFF_TRY(build_lift(g, d_U, d_U_old, ctx->active, ctx->dl, s));
+  PFF_TRY(combine_mask(f.base, ctx->has_extra ? ctx->extra : nullptr, ctx->active, f.mask, g.n_nodes, s));
+  const double* tlift = nullptr;
+  if (*n_active > 0) {
+    PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RAW, ctx->dl, d_U, d_phi_tilde, f.mask, ctx->t, s));
+    tlift = ctx->t;
+  }
+  PFF_TRY(constrain_rhs(g, ctx->R, tlift, ctx->dl, f.mask, ctx->Rt, s));
+  double r2 = 0;
+  PFF_TRY(dot_host(ctx->Rt, ctx->Rt, g.n_dofs, ctx->part, &r2, s));
+  *rt_norm = std::sqrt(r2);
+  return PF_OK;
+}
+
+// Steps 2, 5 and 6 after newton_prepare: level data, FGMRES from the lift, U += dU.
+pf_status newton_solve(pf_ctx* ctx, double* d_U, const double* d_phi_tilde, int* iters, double* rel, double* bn,
+                       hipStream_t s) {
+  const Geom& g = ctx->lev.back().g;
+  PFF_TRY(set_linearization(ctx, d_U, d_phi_tilde, ctx->active, s));
+  PFF_TRY(vec_copy<double>(ctx->dU, ctx->dl, g.n_dofs, s));
+  PFF_TRY(fgmres(ctx, ctx->Rt, ctx->dU, ctx->vprec, iters, rel, bn, s));
+  PFF_TRY(vec_axpby<double>(d_U, 1.0, ctx->dU, 1.0, g.n_dofs, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+bool fgmres_converged(const pf_ctx* ctx, double rel, double bn) {
+  return rel * bn <= std::max(ctx->opt.gmres_rtol * bn, ctx->opt.gmres_atol);
+}
+
 pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde,
                          pf_newton_report* rep, void* stream) {
   NEED_CTX();
@@ -1198,50 +1253,27 @@ pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const 
     return PF_ERR_INVALID_ARG;
   }
   hipStream_t s = st(stream);
-  const int L = (int)ctx->lev.size() - 1;
-  LevelBuf& f = ctx->lev[L];
-  const Geom& g = f.g;
   pf_newton_report r;
   std::memset(&r, 0, sizeof(r));
   const double t0 = now_s();
-  // 1. residual
-  PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RESID, nullptr, d_U, d_phi_tilde, f.mask, ctx->R, s));
-  double bad = 0;
-  PFF_TRY(count_nonfinite(ctx->R, g.n_dofs, ctx->part, &bad, s));
-  if (bad > 0) {
-    set_error("non-finite residual (check U, U_old, phi_tilde)");
+  double rt = 0, t_res = 0;
+  const pf_status sp = newton_prepare(ctx, d_U, d_U_old, d_phi_tilde, &r.n_active, &rt, s, &t_res);
+  if (sp != PF_OK) {
     if (rep) *rep = r;
-    return PF_ERR_NONFINITE;
+    return sp;
   }
-  const double t1 = now_s();
-  // 2-4. active set, lift, level data
-  PFF_TRY(pdas_decide(g, ctx->R, d_U, d_U_old, ctx->M, f.base, ctx->opt.pdas_c, ctx->active, nullptr, s));
-  PFF_TRY(count_bytes(ctx->active, g.n_nodes, ctx->part, &r.n_active, s));
-  PFF_TRY(build_lift(g, d_U, d_U_old, ctx->active, ctx->dl, s));
-  PFF_TRY(set_linearization(ctx, d_U, d_phi_tilde, ctx->active, s));
-  const double* tlift = nullptr;
-  if (r.n_active > 0) {
-    PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RAW, ctx->dl, f.U, f.phit, f.mask, ctx->t, s));
-    tlift = ctx->t;
-  }
-  PFF_TRY(constrain_rhs(g, ctx->R, tlift, ctx->dl, f.mask, ctx->Rt, s));
   PFF_HIP(hipStreamSynchronize(s));
   const double t2 = now_s();
-  // 5. FGMRES from the lift
-  PFF_TRY(vec_copy<double>(ctx->dU, ctx->dl, g.n_dofs, s));
   int iters = 0;
   double rel = 0, bn = 0;
-  PFF_TRY(fgmres(ctx, ctx->Rt, ctx->dU, ctx->vprec, &iters, &rel, &bn, s));
-  // 6. update
-  PFF_TRY(vec_axpby<double>(d_U, 1.0, ctx->dU, 1.0, g.n_dofs, s));
-  PFF_HIP(hipStreamSynchronize(s));
+  PFF_TRY(newton_solve(ctx, d_U, d_phi_tilde, &iters, &rel, &bn, s));
   const double t3 = now_s();
   r.gmres_iters = iters;
   r.rel_residual = rel;
   r.rhs_norm = bn;
-  r.converged = rel <= ctx->opt.gmres_rtol ? 1 : 0;
-  r.t_residual_s = t1 - t0;
-  r.t_setup_s = t2 - t1;
+  r.converged = fgmres_converged(ctx, rel, bn) ? 1 : 0;
+  r.t_residual_s = t_res;
+  r.t_setup_s = t2 - t0 - t_res;
   r.t_solve_s = t3 - t2;
   r.t_total_s = t3 - t0;
   if (rep) *rep = r;
@@ -1249,6 +1281,90 @@ pf_status pf_newton_step(pf_ctx* ctx, double* d_U, const double* d_U_old, const 
     set_error("FGMRES reached gmres_max_iter before the tolerance");
     return PF_ERR_NOT_CONVERGED;
   }
+  return PF_OK;
+}
+
+pf_status pf_pdas_solve(pf_ctx* ctx, double* d_U, const double* d_U_old, const double* d_phi_tilde, int max_iter,
+                        double tol_as, pf_pdas_report* rep, void* stream) {
+  NEED_CTX();
+  if (!d_U || !d_U_old || !d_phi_tilde) {
+    set_error("U, U_old and phi_tilde must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (max_iter < 1 || !(tol_as >= 0.0) || !std::isfinite(tol_as)) {
+    set_error("max_iter must be >= 1 and tol_as finite and >= 0");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = st(stream);
+  const Geom& g = ctx->lev.back().g;
+  pf_pdas_report r;
+  std::memset(&r, 0, sizeof(r));
+  r.n_changed = -1;
+  const double t0 = now_s();
+  pf_status status = PF_ERR_NOT_CONVERGED;
+  bool gmres_failed = false;
+  for (int k = 0; k <= max_iter; ++k) {
+    double rt = 0;
+    const pf_status sp = newton_prepare(ctx, d_U, d_U_old, d_phi_tilde, &r.n_active, &rt, s);
+    if (sp != PF_OK) {
+      status = sp;
+      break;
+    }
+    r.residual_norm = rt;
+    r.n_changed = -1;
+    if (k > 0) PFF_TRY(count_diff_bytes(ctx->active, ctx->prev_active, g.n_nodes, ctx->part, &r.n_changed, s));
+    if (k > 0 && r.n_changed == 0 && rt <= tol_as) {
+      r.converged = 1;
+      status = PF_OK;
+      break;
+    }
+    if (k == max_iter) break;
+    int iters = 0;
+    double rel = 0, bn = 0;
+    PFF_TRY(newton_solve(ctx, d_U, d_phi_tilde, &iters, &rel, &bn, s));
+    r.iterations = k + 1;
+    r.gmres_iters_total += iters;
+    if (!fgmres_converged(ctx, rel, bn)) {
+      set_error("FGMRES reached gmres_max_iter before the tolerance in a PDAS correction");
+      gmres_failed = true;
+      break;
+    }
+    PFF_TRY(vec_copy<uint8_t>(ctx->prev_active, ctx->active, g.n_nodes, s));
+  }
+  PFF_HIP(hipStreamSynchronize(s));
+  r.t_total_s = now_s() - t0;
+  if (rep) *rep = r;
+  if (status == PF_ERR_NOT_CONVERGED && !gmres_failed)
+    set_error("the active set did not settle within max_iter corrections");
+  return status;
+}
+
+pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi_2, double theta, double* d_out,
+                         void* stream) {
+  NEED_CTX();
+  if (!d_phi_1 || !d_phi_2 || !d_out) {
+    set_error("phi_1, phi_2 and out must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (!std::isfinite(theta)) {
+    set_error("theta must be finite");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (d_out == d_phi_1 || d_out == d_phi_2) {
+    set_error("out may not alias phi_1 or phi_2");
+    return PF_ERR_INVALID_ARG;
+  }
+  const LevelBuf& f = ctx->lev.back();
+  return extrapolate_phase(d_phi_1, d_phi_2, theta, f.base, f.g.n_nodes, d_out, st(stream));
+}
+
+pf_status pf_set_pressure(pf_ctx* ctx, double pressure) {
+  NEED_CTX();
+  if (!std::isfinite(pressure)) {
+    set_error("pressure must be finite");
+    return PF_ERR_INVALID_ARG;
+  }
+  ctx->mat.p = pressure;
   return PF_OK;
 }
 

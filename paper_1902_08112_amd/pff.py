@@ -39,13 +39,22 @@ class Options(C.Structure):
                 ("cheb_safety", C.c_double), ("eig_cg_steps", C.c_int), ("coarse_degree", C.c_int),
                 ("coarse_sweeps", C.c_int), ("coarse_lo_factor", C.c_double), ("gmres_restart", C.c_int),
                 ("gmres_max_iter", C.c_int), ("gmres_rtol", C.c_double), ("pdas_c", C.c_double),
-                ("eig_seed", C.c_uint64)]
+                ("eig_seed", C.c_uint64), ("gmres_atol", C.c_double)]
 
 
 class NewtonReport(C.Structure):
     _fields_ = [("gmres_iters", C.c_int), ("converged", C.c_int), ("rel_residual", C.c_double),
                 ("rhs_norm", C.c_double), ("n_active", C.c_int64), ("t_residual_s", C.c_double),
                 ("t_setup_s", C.c_double), ("t_solve_s", C.c_double), ("t_total_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PdasReport(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("gmres_iters_total", C.c_int),
+                ("n_active", C.c_int64), ("n_changed", C.c_int64), ("residual_norm", C.c_double),
+                ("t_total_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +94,9 @@ SIGNATURES = {
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
     "pf_set_kernel_timing": (I, [VP, I]),
+    "pf_pdas_solve": (I, [VP, VP, VP, VP, I, D, C.POINTER(PdasReport), VP]),
+    "pf_extrapolate": (I, [VP, VP, VP, D, VP, VP]),
+    "pf_set_pressure": (I, [VP, D]),
     "pf_get_kernel_timing": (I, [VP, C.POINTER(I), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pf_batch_workspace_size": (I, [C.POINTER(Mesh), I, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "pf_batch_setup": (I, [C.POINTER(Mesh), C.POINTER(D), I, C.POINTER(Options), VP, C.c_size_t, VP,
@@ -227,6 +239,22 @@ def pf_newton_step(ctx, U_ptr, Uold_ptr, phit_ptr, stream=0, raise_on_error=True
     if raise_on_error:
         _check(st, "pf_newton_step")
     return st, rep
+
+
+def pf_pdas_solve(ctx, U_ptr, Uold_ptr, phit_ptr, max_iter=50, tol_as=1e-10, stream=0, raise_on_error=True):
+    rep = PdasReport()
+    st = lib().pf_pdas_solve(ctx, U_ptr, Uold_ptr, phit_ptr, max_iter, tol_as, C.byref(rep), stream)
+    if raise_on_error:
+        _check(st, "pf_pdas_solve")
+    return st, rep
+
+
+def pf_extrapolate(ctx, phi1_ptr, phi2_ptr, theta, out_ptr, stream=0):
+    _check(lib().pf_extrapolate(ctx, phi1_ptr, phi2_ptr, theta, out_ptr, stream), "pf_extrapolate")
+
+
+def pf_set_pressure(ctx, pressure):
+    _check(lib().pf_set_pressure(ctx, pressure), "pf_set_pressure")
 
 
 def pf_get_level_info(ctx, level):
@@ -406,6 +434,34 @@ class Solver:
         st, rep = pf_newton_step(self.ctx, U.data_ptr(), Uold.data_ptr(), phit.data_ptr(), _stream(),
                                  raise_on_error)
         return st, rep
+
+    def pdas_solve(self, U, Uold, phit, max_iter=50, tol_as=1e-10, raise_on_error=True):
+        """Algorithm 1 repeated until the active set settles and ||R~|| <= tol_as (U updated in place)."""
+        return pf_pdas_solve(self.ctx, U.data_ptr(), Uold.data_ptr(), phit.data_ptr(), max_iter, tol_as,
+                             _stream(), raise_on_error)
+
+    def extrapolate(self, phi_1, phi_2, theta=1.0):
+        """phi~ = phi_1 + theta (phi_1 - phi_2) on the finest level's nodes (a new tensor)."""
+        out = self._empty(phi_1.numel(), self.torch.float64)
+        pf_extrapolate(self.ctx, phi_1.data_ptr(), phi_2.data_ptr(), theta, out.data_ptr(), _stream())
+        return out
+
+    def set_pressure(self, pressure):
+        pf_set_pressure(self.ctx, pressure)
+
+    def time_step(self, U_1, U_2, pressure, theta=1.0, first=False, max_iter=50, tol_as=1e-10):
+        """One loading step: U^n from U^{n-1} (U_1) and U^{n-2} (U_2) at pressure p(t_n).
+
+        phi~ is the linear extrapolation of the two previous phase fields (phi^{n-1} at the first
+        step), phi^old = phi^{n-1}, and the PDAS loop starts from U^{n-1}.  Returns (U^n, report)."""
+        nn = self.n_nodes()
+        d = U_1.numel() // nn - 1
+        phi_1, phi_2 = U_1[d * nn:], U_2[d * nn:]
+        phit = phi_1.clone() if first else self.extrapolate(phi_1, phi_2, theta)
+        self.set_pressure(pressure)
+        U = U_1.clone()
+        st, rep = self.pdas_solve(U, U_1, phit, max_iter, tol_as)
+        return U, rep
 
     def set_vcycle_precision(self, prec):
         pf_set_vcycle_precision(self.ctx, prec)
