@@ -333,6 +333,18 @@ def main():
     _, prep = S.pdas_solve(U, dUold, dphit, max_iter=50, tol_as=1e-10, raise_on_error=False)
     torch.cuda.synchronize()
     pdas_out = dict(prep.as_dict(), wall_s=time.perf_counter() - t0)
+    # quantities of interest of the converged state (synchronizing calls, 10 each)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        ec, eb = S.energies(U)
+    t_en = (time.perf_counter() - t0) / 10
+    face = 2 * s["dim"] - 1
+    t0 = time.perf_counter()
+    for _ in range(10):
+        load = S.boundary_traction(U, face)
+    t_ld = (time.perf_counter() - t0) / 10
+    quant = {"crack_energy": ec, "bulk_energy": eb, "energies_s": t_en, "face": face, "face_load": load,
+             "face_load_s": t_ld}
     # plain device copy of a known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
     # in rocprofv3 --pmc runs of this same command (not timed, not part of the result)
     src = torch.rand(n_vec, dtype=torch.float64, device="cuda")
@@ -371,6 +383,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
         "pdas_loop": pdas_out,
+        "quantities": quant,
         "tuning_fine_level": None if tuning is None else tuning["levels"][-1]["choices"],
     }
     S.close()

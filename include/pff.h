@@ -248,6 +248,19 @@ pf_status pf_pdas_solve(pf_ctx* ctx, double* d_U, const double* d_U_old, const d
 pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi_2, double theta, double* d_out,
                          void* stream);
 
+/* Quantities of interest of Sec. 5 for the state d_U = (u, phi) on the
+ * finest level, as reductions over its cells (deterministic order):
+ *   out[0] = crack energy  int G_c/2 ((1 - phi)^2 / eps + eps |grad phi|^2)
+ *   out[1] = bulk energy   int g_kappa(phi) E_s(e(u)) + phi^2 p div u  (no split)
+ * at the cell Gauss points.  out is host memory.  Synchronizes. */
+pf_status pf_energies(pf_ctx* ctx, const double* d_U, double out[2], void* stream);
+/* Load on one face of the box: out[0..dim) = int_face g_kappa(phi) sigma(u) n ds
+ * (n the outward normal; the loading curve of Sec. 5 takes one component).
+ * face = 2k for {x_k = 0}, 2k+1 for {x_k = extent_k}; only facets of active
+ * cells count (the L-shape's hole is not part of the face).  p+1 Gauss points
+ * per tangential direction.  out is host memory.  Synchronizes. */
+pf_status pf_boundary_traction(pf_ctx* ctx, const double* d_U, int face, double* out, void* stream);
+
 /* Set the crack pressure p of the loading (Sec. 5.1: p(t) = 1e3 t); finite.
  * Takes effect at the next operator, residual or set-up call. */
 pf_status pf_set_pressure(pf_ctx* ctx, double pressure);

@@ -27,6 +27,10 @@ pf_status launch_cell_q2_d(const Geom&, const CellParams&, int, const double*, c
                            const uint8_t*, double*, hipStream_t, bool* handled);
 pf_status launch_cell_q2_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
                            const uint8_t*, float*, hipStream_t, bool* handled);
+pf_status quantity_energies(const Geom& gm, const CellParams& cp, double Gc, double eps, const double* U,
+                            double* d_part, double out[2], hipStream_t s);
+pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face, const double* U, double* d_part,
+                                 double* out, hipStream_t s);
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
@@ -168,6 +172,7 @@ struct pf_ctx {
   std::vector<hipEvent_t> aux_ev;
   hipEvent_t fork_ev = nullptr;
   double* part_lev = nullptr;
+  double* qpart = nullptr;      // reduction scratch of the quantities of interest
   double* host_scal = nullptr;  // pinned host copy of the FGMRES scalars (kHostScal doubles)
   // optional HIP-event timing of the finest-level FP64 Jacobian cell kernel (pf_set_kernel_timing)
   bool ktime_on = false;
@@ -370,6 +375,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* dscal = cv.take<double>(1024);
   EigDev* eigdev = cv.take<EigDev>(L);
   double* part_lev = cv.take<double>((size_t)L * kPartStride);
+  double* qpart = cv.take<double>(3 * 1024 + 64);
   double* vin = cv.take<double>(nd);
   double* vout = cv.take<double>(nd);
   if (c) {
@@ -390,6 +396,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->dscal = dscal;
     c->eigdev = eigdev;
     c->part_lev = part_lev;
+    c->qpart = qpart;
     c->vin = vin;
     c->vout = vout;
   }
@@ -1356,6 +1363,32 @@ pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi
   }
   const LevelBuf& f = ctx->lev.back();
   return extrapolate_phase(d_phi_1, d_phi_2, theta, f.base, f.g.n_nodes, d_out, st(stream));
+}
+
+pf_status pf_energies(pf_ctx* ctx, const double* d_U, double out[2], void* stream) {
+  NEED_CTX();
+  if (!d_U || !out) {
+    set_error("U and out must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int L = (int)ctx->lev.size() - 1;
+  return quantity_energies(ctx->lev[L].g, cparams(ctx, L), ctx->mat.Gc, ctx->mat.eps, d_U, ctx->qpart, out,
+                           st(stream));
+}
+
+pf_status pf_boundary_traction(pf_ctx* ctx, const double* d_U, int face, double* out, void* stream) {
+  NEED_CTX();
+  const int L = (int)ctx->lev.size() - 1;
+  const Geom& g = ctx->lev[L].g;
+  if (!d_U || !out) {
+    set_error("U and out must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (face < 0 || face >= 2 * g.d) {
+    set_error("face must be in [0, 2 dim)");
+    return PF_ERR_INVALID_ARG;
+  }
+  return quantity_face_traction(g, cparams(ctx, L), face, d_U, ctx->qpart, out, st(stream));
 }
 
 pf_status pf_set_pressure(pf_ctx* ctx, double pressure) {

@@ -97,6 +97,8 @@ SIGNATURES = {
     "pf_pdas_solve": (I, [VP, VP, VP, VP, I, D, C.POINTER(PdasReport), VP]),
     "pf_extrapolate": (I, [VP, VP, VP, D, VP, VP]),
     "pf_set_pressure": (I, [VP, D]),
+    "pf_energies": (I, [VP, VP, C.POINTER(D), VP]),
+    "pf_boundary_traction": (I, [VP, VP, I, C.POINTER(D), VP]),
     "pf_get_kernel_timing": (I, [VP, C.POINTER(I), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pf_batch_workspace_size": (I, [C.POINTER(Mesh), I, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "pf_batch_setup": (I, [C.POINTER(Mesh), C.POINTER(D), I, C.POINTER(Options), VP, C.c_size_t, VP,
@@ -448,6 +450,20 @@ class Solver:
 
     def set_pressure(self, pressure):
         pf_set_pressure(self.ctx, pressure)
+
+    def energies(self, U):
+        """(crack energy, bulk energy) of the state U (finest level, FP64)."""
+        out = (D * 2)()
+        _check(lib().pf_energies(self.ctx, U.data_ptr(), out, _stream()), "pf_energies")
+        return out[0], out[1]
+
+    def boundary_traction(self, U, face):
+        """int over box face `face` (2k: x_k = 0, 2k+1: x_k = extent_k) of g(phi) sigma(u) n."""
+        out = (D * 3)()
+        _check(lib().pf_boundary_traction(self.ctx, U.data_ptr(), face, out, _stream()), "pf_boundary_traction")
+        nn = self.n_nodes()
+        d = U.numel() // nn - 1
+        return [out[i] for i in range(d)]
 
     def time_step(self, U_1, U_2, pressure, theta=1.0, first=False, max_iter=50, tol_as=1e-10):
         """One loading step: U^n from U^{n-1} (U_1) and U^{n-2} (U_2) at pressure p(t_n).
