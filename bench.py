@@ -244,12 +244,13 @@ def main():
     dphit = torch.from_numpy(phit).cuda()
     U = torch.empty_like(dU0)
 
-    def run_steps(k, prec):
-        S.set_vcycle_precision(prec)
+    def run_steps(k, prec, solver=None):
+        solver = solver or S
+        solver.set_vcycle_precision(prec)
         reps = []
         for _ in range(k):
             U.copy_(dU0)
-            st, rep = S.newton_step(U, dUold, dphit)
+            st, rep = solver.newton_step(U, dUold, dphit)
             reps.append(rep.as_dict())
         return reps
 
@@ -345,6 +346,25 @@ def main():
     t_ld = (time.perf_counter() - t0) / 10
     quant = {"crack_energy": ec, "bulk_energy": eb, "energies_s": t_en, "face": face, "face_load": load,
              "face_load_s": t_ld}
+    # the alternative preconditioner P_diag = diag(MG(U~), MG(P~)) (Sec. 3.3): the same Newton
+    # step from the same iterate in the workload's V-cycle precision, on its own tuned context
+    S.close()
+    Sd = pff.solver_from_spec(s, preconditioner=pff.PF_PREC_DIAG)
+    if bits is not None:
+        Sd.set_constraints(torch.from_numpy(bits).cuda())
+    run_steps(1, base_prec, Sd)
+    if not a.no_tune:
+        Sd.autotune(reps=10)
+    run_steps(a.warmup, base_prec, Sd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps_d = run_steps(a.steps, base_prec, Sd)
+    torch.cuda.synchronize()
+    t_diag = (time.perf_counter() - t0) / a.steps
+    pdiag = {"newton_s": t_diag, "gmres_iters": reps_d[-1]["gmres_iters"],
+             "converged": reps_d[-1]["converged"], "rel_residual": reps_d[-1]["rel_residual"],
+             "p_full_newton_s": t_base, "p_full_gmres_iters": reps[-1]["gmres_iters"]}
+    Sd.close()
     # plain device copy of a known size: the scale of the FETCH_SIZE / WRITE_SIZE counters
     # in rocprofv3 --pmc runs of this same command (not timed, not part of the result)
     src = torch.rand(n_vec, dtype=torch.float64, device="cuda")
@@ -384,9 +404,9 @@ def main():
         "cpu_baseline": None,
         "pdas_loop": pdas_out,
         "quantities": quant,
+        "p_diag": pdiag,
         "tuning_fine_level": None if tuning is None else tuning["levels"][-1]["choices"],
     }
-    S.close()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, a.cpu_sample)
     print(json.dumps(out), flush=True)

@@ -57,6 +57,13 @@ typedef int pf_status;
 #define PF_F64 0
 #define PF_F32 1
 
+/* Preconditioner structure (Sec. 3.3): PF_PREC_FULL = MG(G~), one multigrid on the whole
+ * system with the block smoother; PF_PREC_DIAG = diag(MG(U~), MG(P~)), one multigrid per
+ * diagonal block (every residual inside the cycle is formed with the block-diagonal B~, so
+ * the coupling block G_phi,u is not seen by the preconditioner). */
+#define PF_PREC_FULL 0
+#define PF_PREC_DIAG 1
+
 #define PF_BOX 0
 #define PF_LSHAPE 1 /* [0,1]^3 minus [0.5,1]x[0.5,1]x[0,1] (2D: the same without z), scaled by extent */
 
@@ -95,6 +102,7 @@ typedef struct pf_options {
   uint64_t eig_seed;       /* SplitMix64 seed of the eigenvalue start vectors */
   double gmres_atol;       /* absolute floor of the FGMRES stop (default 0; the inexact solves of
                               Sec. 5 use rtol 1e-4 with a small floor) */
+  int preconditioner;      /* PF_PREC_FULL (default, the paper's choice) or PF_PREC_DIAG */
 } pf_options;
 
 typedef struct pf_newton_report {

@@ -11,7 +11,11 @@
 * Chebyshev-Jacobi smoothing over [1.2 lam/5, 1.2 lam] with degree 4
   (Sec. 3.2.1) and the Chebyshev coarse solve over [0.9 lam_min, 1.2 lam_max]
   (Sec. 3.2.2);
-* the V-cycle P_full^{-1} = MG(G~) (Sec. 3.3).
+* the V-cycle P_full^{-1} = MG(G~) (Sec. 3.3), and the block-diagonal
+  alternative P_diag^{-1} = diag(MG(U~), MG(P~)) of the same section: one
+  multigrid per diagonal block, i.e. the same cycle with every residual formed
+  with B~ instead of G~ (the transfers, smoothers and coarse solves are per
+  block already, so the two block cycles never mix).
 """
 from __future__ import annotations
 
@@ -125,6 +129,7 @@ class Options:
     gmres_atol: float = 0.0          # absolute floor: stop at max(rtol ||R~||, atol)
     pdas_c: float = 100.0
     eig_seed: int = 12345
+    preconditioner: str = "full"     # "full": MG(G~); "diag": diag(MG(U~), MG(P~)) (Sec. 3.3)
 
 
 @dataclass
@@ -218,10 +223,18 @@ class Hierarchy:
         return out
 
     # ------------------------------------------------------------------
+    def cycle_operator(self, l):
+        """The operator the V-cycle forms its residuals with: G~ for P_full, B~ for P_diag."""
+        if self.opts.preconditioner == "full":
+            return self.mg[l].G
+        if self.opts.preconditioner == "diag":
+            return self.mg[l].B
+        raise ValueError(f"unknown preconditioner {self.opts.preconditioner!r}")
+
     def smooth(self, l, b, x):
-        """One smoothing step: r = b - G~ x (full operator), x += Cheb_B(r) per block."""
+        """One smoothing step: r = b - G~ x (the cycle's operator), x += Cheb_B(r) per block."""
         m = self.mg[l]
-        r = b - m.G @ x
+        r = b - self.cycle_operator(l) @ x
         e = np.zeros_like(x)
         o = self.opts
         for name, idx in self.blocks(l).items():
@@ -234,8 +247,9 @@ class Hierarchy:
         m = self.mg[0]
         o = self.opts
         x = np.zeros_like(b)
+        A = self.cycle_operator(0)
         for _ in range(o.coarse_sweeps):
-            r = b - m.G @ x
+            r = b - A @ x
             for name, idx in self.blocks(0).items():
                 lo = o.coarse_lo_factor * m.eig[name][0]
                 hi = o.cheb_safety * m.eig[name][1]
@@ -247,7 +261,7 @@ class Hierarchy:
             return self.coarse_solve(b)
         m = self.mg[l]
         x = self.smooth(l, b, np.zeros_like(b))
-        r = b - m.G @ x
+        r = b - self.cycle_operator(l) @ x
         bc = self.P[l].T @ r
         bc[self.mg[l - 1].constrained] = 0.0
         e = self.vcycle_level(l - 1, bc)
@@ -257,7 +271,7 @@ class Hierarchy:
         return self.smooth(l, b, x)
 
     def vcycle(self, r):
-        """z = P_full^{-1} r on the fine level; input and output vanish on constrained DoFs."""
+        """z = P^{-1} r on the fine level (P_full or P_diag); input and output vanish on constrained DoFs."""
         L = len(self.levels) - 1
         c = self.mg[L].constrained
         b = np.where(c, 0.0, r)

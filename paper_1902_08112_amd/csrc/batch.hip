@@ -738,6 +738,9 @@ pf_status bcheb(pf_batch* c, int l, int prec, T* res, T* x, const double* coef, 
   return PF_OK;
 }
 
+// residual operator of the V-cycle: G~ (P_full) or the block-diagonal B~ (P_diag), Sec. 3.3
+int bcycle_mode(const pf_batch* c) { return c->opt.preconditioner == PF_PREC_DIAG ? MODE_BLOCK : MODE_APPLY; }
+
 template <typename T>
 pf_status bsmooth(pf_batch* c, int l, int prec, bool x_zero, hipStream_t s) {
   BLevel& bl = c->lev[l];
@@ -747,7 +750,7 @@ pf_status bsmooth(pf_batch* c, int l, int prec, bool x_zero, hipStream_t s) {
   if (x_zero) {
     PFF_TRY(vec_sub<T>(r, bb, x, bl.n_dofs, s));  // x == 0: r = b
   } else {
-    PFF_TRY(bapply(c, l, prec, MODE_APPLY, x, bl.vt, s));
+    PFF_TRY(bapply(c, l, prec, bcycle_mode(c), x, bl.vt, s));
     PFF_TRY(vec_sub<T>(r, bb, (T*)bl.vt, bl.n_dofs, s));
   }
   return bcheb<T>(c, l, prec, r, x, bl.d_coef_s, c->opt.cheb_degree, s);
@@ -763,7 +766,7 @@ pf_status bcoarse(pf_batch* c, hipStream_t s) {
     if (sw == 0) {
       PFF_TRY(vec_sub<double>(r, bb, x, bl.n_dofs, s));
     } else {
-      PFF_TRY(bapply(c, 0, PF_F64, MODE_APPLY, x, bl.vt, s));
+      PFF_TRY(bapply(c, 0, PF_F64, bcycle_mode(c), x, bl.vt, s));
       PFF_TRY(vec_sub<double>(r, bb, (double*)bl.vt, bl.n_dofs, s));
     }
     PFF_TRY(bcheb<double>(c, 0, PF_F64, r, x, bl.d_coef_c, c->opt.coarse_degree, s));
@@ -795,13 +798,13 @@ pf_status bvcycle_level(pf_batch* c, int l, int vprec, hipStream_t s) {
   if (pl == PF_F64) {
     PFF_TRY(vec_fill<double>((double*)bl.vx, 0.0, bl.n_dofs, s));
     PFF_TRY(bsmooth<double>(c, l, pl, true, s));
-    PFF_TRY(bapply(c, l, pl, MODE_APPLY, bl.vx, bl.vt, s));
+    PFF_TRY(bapply(c, l, pl, bcycle_mode(c), bl.vx, bl.vt, s));
     PFF_TRY(vec_sub<double>((double*)bl.vr, (double*)bl.vb, (double*)bl.vt, bl.n_dofs, s));
     PFF_TRY(pc == PF_F64 ? brestrict<double, double>(c, l, s) : brestrict<double, float>(c, l, s));
   } else {
     PFF_TRY(vec_fill<float>((float*)bl.vx, 0.0f, bl.n_dofs, s));
     PFF_TRY(bsmooth<float>(c, l, pl, true, s));
-    PFF_TRY(bapply(c, l, pl, MODE_APPLY, bl.vx, bl.vt, s));
+    PFF_TRY(bapply(c, l, pl, bcycle_mode(c), bl.vx, bl.vt, s));
     PFF_TRY(vec_sub<float>((float*)bl.vr, (float*)bl.vb, (float*)bl.vt, bl.n_dofs, s));
     PFF_TRY(pc == PF_F64 ? brestrict<float, double>(c, l, s) : brestrict<float, float>(c, l, s));
   }

@@ -46,7 +46,8 @@ __device__ void wg_apply(const CellParams& cp, const double* x, double* y, const
   __syncthreads();
 }
 
-template <int D>
+// COUPLE: the sweep residuals b - A x use the full G~ (P_full) or the block-diagonal B~ (P_diag)
+template <int D, bool COUPLE>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, CoarseCoef cc, const double* U,
                                                                  const double* phit, const uint8_t* mask,
                                                                  const double* diag, const double* b, double* x,
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
     } else {
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) vd[i] = x[i];
       __syncthreads();
-      wg_apply<D, true>(cp, vd, vt, U, phit, mask);
+      wg_apply<D, COUPLE>(cp, vd, vt, U, phit, mask);
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = b[i] - vt[i];
     }
     for (int k = 0; k < cc.degree; ++k) {
@@ -86,11 +87,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
   }
 }
 
-// Q1 levels up to kCoarseMaxDofs and degrees up to kCoarseMaxDegree; *handled = false otherwise
+// Q1 levels up to kCoarseMaxDofs and degrees up to kCoarseMaxDegree; *handled = false otherwise.
+// couple: sweep residuals with G~ (P_full) or with B~ (P_diag)
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, hipStream_t s, bool* handled) {
+                              double* x, double* r, bool couple, hipStream_t s, bool* handled) {
   *handled = false;
   if (g.p != 1 || degree > kCoarseMaxDegree || degree < 1 || g.n_dofs > kCoarseMaxDofs) return PF_OK;
   CoarseCoef cc;
@@ -103,10 +105,14 @@ pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, i
     cc.c2[1][k] = c2p[k];
   }
   const size_t lds = 2 * (size_t)g.n_dofs * sizeof(double);
-  if (g.d == 2)
-    k_coarse_solve<2><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  if (g.d == 2 && couple)
+    k_coarse_solve<2, true><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  else if (g.d == 2)
+    k_coarse_solve<2, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  else if (couple)
+    k_coarse_solve<3, true><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
   else
-    k_coarse_solve<3><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    k_coarse_solve<3, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
   PFF_CHECK_LAUNCH();
   *handled = true;
   return PF_OK;

@@ -34,7 +34,7 @@ pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face,
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, hipStream_t s, bool* handled);
+                              double* x, double* r, bool couple, hipStream_t s, bool* handled);
 
 template <>
 pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
@@ -300,6 +300,10 @@ pf_status validate_opts(const pf_options* o) {
     set_error("pdas_c must be finite and >= 0");
     return PF_ERR_INVALID_ARG;
   }
+  if (o->preconditioner != PF_PREC_FULL && o->preconditioner != PF_PREC_DIAG) {
+    set_error("preconditioner must be PF_PREC_FULL or PF_PREC_DIAG");
+    return PF_ERR_INVALID_ARG;
+  }
   return PF_OK;
 }
 
@@ -499,6 +503,12 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
   return PF_OK;
 }
 
+// The operator the V-cycle forms its residuals with: G~ for P_full = MG(G~), the
+// block-diagonal B~ for P_diag = diag(MG(U~), MG(P~)) (Sec. 3.3).  The transfers, the
+// smoother and the coarse Chebyshev work per block in both, so with B~ the two block
+// multigrids run side by side without ever mixing.
+int cycle_mode(const pf_ctx* c) { return c->opt.preconditioner == PF_PREC_DIAG ? MODE_BLOCK : MODE_APPLY; }
+
 // one smoothing step x += Cheb_B(b - G~ x); x_zero: x = 0 on entry (x is not read).
 // tail_init: leave t = Pi_C x for a following G~ x apply.
 template <typename T>
@@ -507,7 +517,7 @@ pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, bool tail_init, hipStr
   T* bb = (T*)b.vb;
   T* x = (T*)b.vx;
   T* r = (T*)b.vr;
-  if (!x_zero) PFF_TRY(level_apply(c, l, prec, MODE_APPLY, x, b.vt, s));
+  if (!x_zero) PFF_TRY(level_apply(c, l, prec, cycle_mode(c), x, b.vt, s));
   const pf_options& o = c->opt;
   const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
   const double lo[2] = {hi[0] / o.cheb_ratio, hi[1] / o.cheb_ratio};
@@ -526,11 +536,12 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
     const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
     bool handled = false;
     PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
-                                cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, bb, x, r, s, &handled));
+                                cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, bb, x, r,
+                                cycle_mode(c) == MODE_APPLY, s, &handled));
     if (handled) return PF_OK;
   }
   for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
-    if (sw > 0) PFF_TRY(level_apply(c, 0, PF_F64, MODE_APPLY, x, b.vt, s));
+    if (sw > 0) PFF_TRY(level_apply(c, 0, PF_F64, cycle_mode(c), x, b.vt, s));
     // sweep 0 starts from x = 0 (r = b), later sweeps from r = b - G~ x
     PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, sw == 0 ? 1 : 2, bb, false, s));
   }
@@ -557,14 +568,15 @@ pf_status vcycle_level(pf_ctx* c, int l, int vprec, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   // pre-smoothing from x = 0; its last step leaves t = Pi_C x when the residual apply needs it,
   // and the residual b - G~ x is formed inside the restriction
-  const bool pre_init = apply_needs_preset(c, l, pl, MODE_APPLY);
+  const int cm = cycle_mode(c);
+  const bool pre_init = apply_needs_preset(c, l, pl, cm);
   if (pl == PF_F64) {
     PFF_TRY(smooth<double>(c, l, pl, true, pre_init, s));
-    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s, pre_init));
+    PFF_TRY(level_apply(c, l, pl, cm, b.vx, b.vt, s, pre_init));
     PFF_TRY(pc == PF_F64 ? restrict_to<double, double>(c, l, s) : restrict_to<double, float>(c, l, s));
   } else {
     PFF_TRY(smooth<float>(c, l, pl, true, pre_init, s));
-    PFF_TRY(level_apply(c, l, pl, MODE_APPLY, b.vx, b.vt, s, pre_init));
+    PFF_TRY(level_apply(c, l, pl, cm, b.vx, b.vt, s, pre_init));
     PFF_TRY(pc == PF_F64 ? restrict_to<float, double>(c, l, s) : restrict_to<float, float>(c, l, s));
   }
   PFF_TRY(vcycle_level(c, l - 1, vprec, s));
@@ -875,6 +887,7 @@ void pf_default_options(pf_options* o) {
   o->gmres_atol = 0.0;
   o->pdas_c = 100.0;
   o->eig_seed = 12345;
+  o->preconditioner = PF_PREC_FULL;
 }
 
 const char* pf_status_string(pf_status s) {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libpff.so")
 PF_OK, PF_ERR_INVALID_ARG, PF_ERR_UNSUPPORTED, PF_ERR_DEVICE = 0, 1, 2, 3
 PF_ERR_WORKSPACE, PF_ERR_NOT_CONVERGED, PF_ERR_NONFINITE = 4, 5, 6
 PF_F64, PF_F32 = 0, 1
+PF_PREC_FULL, PF_PREC_DIAG = 0, 1
 PF_BOX, PF_LSHAPE = 0, 1
 PF_MASK_PHI = 8
 
@@ -39,7 +40,7 @@ class Options(C.Structure):
                 ("cheb_safety", C.c_double), ("eig_cg_steps", C.c_int), ("coarse_degree", C.c_int),
                 ("coarse_sweeps", C.c_int), ("coarse_lo_factor", C.c_double), ("gmres_restart", C.c_int),
                 ("gmres_max_iter", C.c_int), ("gmres_rtol", C.c_double), ("pdas_c", C.c_double),
-                ("eig_seed", C.c_uint64), ("gmres_atol", C.c_double)]
+                ("eig_seed", C.c_uint64), ("gmres_atol", C.c_double), ("preconditioner", C.c_int)]
 
 
 class NewtonReport(C.Structure):

@@ -152,6 +152,67 @@ def test_two_grid_contraction_on_phase_field_block():
         x = x_new
 
 
+@pytest.mark.parametrize("name", ["small2d", "tiny3d_q2", "small_lshape"])
+def test_block_diagonal_vcycle_against_the_full_one(name):
+    """P_diag = diag(MG(U~), MG(P~)) (Sec. 3.3) pinned to the full cycle through the structure of G~.
+
+    G_u,phi = 0 (time-lagged phi~), so G~ is block lower triangular: the u rows of every
+    residual inside P_full never see the phi part, and its u output equals MG(U~).  With
+    r_u = 0 the u part of the full cycle stays 0, the coupling G_phi,u x_u vanishes, and its
+    phi output equals MG(P~) r_phi.  P_diag must be exactly that, block by block.
+    """
+    s, H = hierarchy(name)
+    U, phit = W.random_linearization(s, 1)
+    act = W.random_active(s, 2, 0.1)
+    H.set_linearization(U, phit, act)
+    fine = H.fine
+    du = fine.d * fine.n_nodes
+    G = H.mg[-1].G
+    assert abs(G[:du, du:]).max() == 0.0 and abs(G[du:, :du]).max() > 0.0
+    n = fine.n_dofs
+    r = np.random.default_rng(8).uniform(-1, 1, n)
+    ru, rp = r.copy(), r.copy()
+    ru[du:] = 0.0
+    rp[:du] = 0.0
+    H.opts.preconditioner = "full"
+    zf, zf_p = H.vcycle(r), H.vcycle(rp)
+    zf_u = H.vcycle(ru)
+    H.opts.preconditioner = "diag"
+    zd, zd_u, zd_p = H.vcycle(r), H.vcycle(ru), H.vcycle(rp)
+    scale = np.abs(zf).max()
+    assert np.allclose(zd[:du], zf[:du], rtol=0, atol=1e-13 * scale)
+    assert np.allclose(zd[du:], zf_p[du:], rtol=0, atol=1e-13 * scale)
+    # block diagonal: neither block's input reaches the other block's output
+    assert np.abs(zd_u[du:]).max() <= 1e-14 * scale and np.abs(zd_p[:du]).max() <= 1e-14 * scale
+    # while the full cycle does carry r_u into the phi part (through G_phi,u)
+    assert np.abs(zf_u[du:]).max() > 1e-6 * scale
+    # P_diag contracts on the block operator it inverts
+    B = H.mg[-1].B
+    c = H.mg[-1].constrained
+    x = np.where(c, 0, np.random.default_rng(9).uniform(-1, 1, n))
+    e1 = x - H.vcycle(B @ x)
+    assert np.linalg.norm(e1) < 0.9 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("name", ["tiny2d", "tiny3d"])
+def test_newton_step_with_block_diagonal_preconditioner(name):
+    """FGMRES preconditioned by P_diag reaches the same Newton update as the dense solve."""
+    s, H = hierarchy(name, opts=mg.Options(preconditioner="diag"))
+    U, Uold, phit = W.make_state(s)
+    dense = newton.newton_step(H, U, Uold, phit, solver="dense")
+    it = newton.newton_step(H, U, Uold, phit, solver="fgmres")
+    assert it["rel_res"] <= 1e-8
+    assert np.linalg.norm(it["dU"] - dense["dU"]) <= 1e-6 * np.linalg.norm(dense["dU"])
+
+
+def test_unknown_preconditioner_is_rejected():
+    s, H = hierarchy("tiny2d", opts=mg.Options(preconditioner="blocks"))
+    U, phit = W.random_linearization(s, 1)
+    H.set_linearization(U, phit)
+    with pytest.raises(ValueError):
+        H.vcycle(np.ones(H.fine.n_dofs))
+
+
 # ---------------------------------------------------------------------------
 # Newton / PDAS
 # ---------------------------------------------------------------------------
