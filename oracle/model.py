@@ -1,10 +1,21 @@
 """Residual A(U), Jacobian G(U), lumped mass and constraints (oracle, test infrastructure only).
 
 Follows the quasi-monolithic semi-linear form (Sec. 2.3, eq. semilinear) with
-no stress split (E_s^+ = E_s, sigma^- = 0), the time-lagged extrapolation
-phi~ in the displacement equation, and its discrete Jacobian
-G_ij = A'(U)(Phi_i, Phi_j) (Sec. 2.4).  Everything is computed by per-cell
-Gauss quadrature into dense element arrays and assembled into SciPy CSR.
+either no stress split (E_s^+ = E_s, sigma^- = 0) or the Miehe spectral split
+(Sec. 2.1), the time-lagged extrapolation phi~ in the displacement equation,
+and its discrete Jacobian G_ij = A'(U)(Phi_i, Phi_j) (Sec. 2.4).  Everything is
+computed by per-cell Gauss quadrature into dense element arrays and assembled
+into SciPy CSR.
+
+Miehe split (Sec. 2.1): with e = sum_i lam_i n_i n_i^T,
+  E_s^+ = lam/2 <tr e>_+^2 + mu tr(e_+^2),  e_+ = sum_i <lam_i>_+ n_i n_i^T,
+  sigma^+ = dE_s^+/de = lam <tr e>_+ I + 2 mu e_+,  E_s^- = E_s - E_s^+,
+  sigma^- = sigma - sigma^+.
+Its tangent dsigma^+/de [h] = lam H(tr e) tr(h) I + 2 mu De_+[h], where the
+derivative of the spectral function e -> e_+ is the Daleckii-Krein formula
+De_+[h] = N (F o (N^T h N)) N^T with F_ij the divided difference of <.>_+ at
+(lam_i, lam_j) (its derivative H(lam_i) when lam_i = lam_j); the eigenpairs come
+from numpy.linalg.eigh.
 
 Readings of the paper used here (also listed in the design notes):
 * the factor 1/2 in front of d_phi g_kappa(phi) E_s in the phase-field
@@ -14,7 +25,12 @@ Readings of the paper used here (also listed in the design notes):
   which makes the u/phi block of the Jacobian zero (Sec. 3.3);
 * 2D is plane strain: lambda = E nu / ((1+nu)(1-2nu)) in every dimension
   (the multiple-fracture parameter table lists mu = 4166.6, lambda = 2777.7
-  for E = 1e4, nu = 0.2).
+  for E = 1e4, nu = 0.2);
+* split: the Heaviside step H = d<x>_+/dx is taken as 0 at x = 0 (a zero
+  eigenvalue or trace counts as not in tension; at e = 0 the tangent is the
+  undegraded C), and in 2D the split acts on the in-plane 2x2 strain (the
+  out-of-plane eigenvalue of plane strain is 0 and adds nothing to e_+, tr e,
+  or the in-plane tangent).
 """
 from __future__ import annotations
 
@@ -36,6 +52,7 @@ class Material:
     eps: float
     kappa: float
     pressure: float
+    split: str = "none"     # "none" (E_s^+ = E_s) or "miehe" (spectral split, Sec. 2.1)
 
     @property
     def mu(self) -> float:
@@ -56,6 +73,50 @@ class Material:
 
     def d2g(self, s):
         return 2.0 * (1.0 - self.kappa) + 0.0 * s
+
+
+# --------------------------------------------------------------------------
+# Miehe spectral split (Sec. 2.1)
+# --------------------------------------------------------------------------
+def positive_part(x):
+    """<x>_+ = max(0, x)."""
+    return np.maximum(x, 0.0)
+
+
+def heaviside(x):
+    """d<x>_+/dx, taken as 0 at x = 0."""
+    return (x > 0.0).astype(np.float64)
+
+
+def miehe_split(mat: Material, e):
+    """Positive parts of the Miehe split at strains e (..., d, d).
+
+    Returns the eigenpairs, tr e, E_s^+, sigma^+, the divided-difference matrix F of
+    <.>_+ at the eigenvalue pairs and H(tr e) (what the tangent needs).
+    """
+    d = e.shape[-1]
+    lam_i, N = np.linalg.eigh(e)                       # ascending, eigenvectors in columns
+    tr = np.trace(e, axis1=-2, axis2=-1)
+    lp = positive_part(lam_i)
+    e_pos = np.einsum("...ia,...a,...ja->...ij", N, lp, N)
+    Es_pos = 0.5 * mat.lam * positive_part(tr) ** 2 + mat.mu * np.sum(lp * lp, axis=-1)
+    sigma_pos = mat.lam * positive_part(tr)[..., None, None] * np.eye(d) + 2.0 * mat.mu * e_pos
+    li, lj = lam_i[..., :, None], lam_i[..., None, :]
+    same = li == lj
+    F = np.where(same, heaviside(np.broadcast_to(li, same.shape)),
+                 (positive_part(li) - positive_part(lj)) / np.where(same, 1.0, li - lj))
+    return dict(lam=lam_i, N=N, tr=tr, e_pos=e_pos, Es_pos=Es_pos, sigma_pos=sigma_pos, F=F,
+                H_tr=heaviside(tr))
+
+
+def tangent_pos(mat: Material, sp, h):
+    """dsigma^+/de [h] for strain increments h (..., k, d, d) at the split sp (shape ...)."""
+    d = h.shape[-1]
+    N = sp["N"][..., None, :, :]
+    ht = np.einsum("...ai,...ab,...bj->...ij", N, h, N)            # N^T h N
+    De = np.einsum("...ia,...ab,...jb->...ij", N, sp["F"][..., None, :, :] * ht, N)
+    trh = np.trace(h, axis1=-2, axis2=-1)
+    return mat.lam * (sp["H_tr"][..., None] * trh)[..., None, None] * np.eye(d) + 2.0 * mat.mu * De
 
 
 # --------------------------------------------------------------------------
@@ -100,7 +161,14 @@ def qp_state(lev: Level, tab: CellTables, mat: Material, U, phit, cells):
     phi = np.einsum("qa,ca->cq", tab.N, phie)
     grad_phi = np.einsum("qaj,ca->cqj", tab.dN, phie)
     phit_q = np.einsum("qa,ca->cq", tab.N, ptle)
-    return dict(e=e, sigma=sigma, Es=Es, div_u=tr, phi=phi, grad_phi=grad_phi, phit=phit_q)
+    out = dict(e=e, sigma=sigma, Es=Es, div_u=tr, phi=phi, grad_phi=grad_phi, phit=phit_q,
+               Es_pos=Es, sigma_pos=sigma, split=None)
+    if mat.split == "miehe":
+        sp = miehe_split(mat, e)
+        out.update(Es_pos=sp["Es_pos"], sigma_pos=sp["sigma_pos"], split=sp)
+    elif mat.split != "none":
+        raise ValueError(f"unknown split {mat.split!r}")
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -109,16 +177,18 @@ def qp_state(lev: Level, tab: CellTables, mat: Material, U, phit, cells):
 def element_residual(lev, tab, mat, U, phit, cells):
     """Element vectors of A(U)(Phi_i) on the given cells: (nc, (d+1) nl).
 
-    u rows:   (g(phi~) sigma(u), e(w)) + (phi~^2 p, div w)
-    phi rows: (1/2 g'(phi) E_s(e(u)) + 2 phi p div u - G_c/eps (1-phi), psi)
+    u rows:   (g(phi~) sigma^+(u) + sigma^-(u), e(w)) + (phi~^2 p, div w)
+    phi rows: (1/2 g'(phi) E_s^+(e(u)) + 2 phi p div u - G_c/eps (1-phi), psi)
               + G_c eps (grad phi, grad psi)
     """
     s = qp_state(lev, tab, mat, U, phit, cells)
     p = mat.pressure
     gq = mat.g(s["phit"])
-    ru = np.einsum("q,cq,cqij,qkij->ck", tab.JxW, gq, s["sigma"], tab.eps_w)
+    # g sigma^+ + sigma^- = sigma - (1 - g) sigma^+
+    sig_u = s["sigma"] - (1.0 - gq)[..., None, None] * s["sigma_pos"]
+    ru = np.einsum("q,cqij,qkij->ck", tab.JxW, sig_u, tab.eps_w)
     ru += np.einsum("q,cq,qk->ck", tab.JxW, s["phit"] ** 2 * p, tab.div_w)
-    val = (ES_FACTOR * mat.dg(s["phi"]) * s["Es"] + 2.0 * s["phi"] * p * s["div_u"]
+    val = (ES_FACTOR * mat.dg(s["phi"]) * s["Es_pos"] + 2.0 * s["phi"] * p * s["div_u"]
            - mat.G_c / mat.eps * (1.0 - s["phi"]))
     rphi = np.einsum("q,cq,qa->ca", tab.JxW, val, tab.N)
     rphi += mat.G_c * mat.eps * np.einsum("q,cqj,qaj->ca", tab.JxW, s["grad_phi"], tab.dN)
@@ -129,10 +199,11 @@ def element_jacobian(lev, tab, mat, U, phit, cells, couple=True):
     """Dense element Jacobians A'(U)(Phi_i, Phi_j) on the given cells: (nc, nloc, nloc).
 
     Blocks (rows = test, cols = trial):
-      uu:     (g(phi~) sigma(du), e(w))
+      uu:     (g(phi~) C^+[e(du)] + C^-[e(du)], e(w)), C^+- = dsigma^+-/de at e(u)
+              (no split: C^+ = C, so g(phi~) sigma(du))
       u phi:  0   (phi~ is fixed; Sec. 3.3)
-      phi u:  (1/2 g'(phi) sigma(u):e(du) + 2 phi p div du, psi)
-      phi phi:(1/2 g''(phi) E_s(e(u)) dphi + 2 p div u dphi + G_c/eps dphi, psi)
+      phi u:  (1/2 g'(phi) sigma^+(u):e(du) + 2 phi p div du, psi)
+      phi phi:(1/2 g''(phi) E_s^+(e(u)) dphi + 2 p div u dphi + G_c/eps dphi, psi)
               + G_c eps (grad dphi, grad psi)
     couple=False drops the phi-u block (the block-diagonal operator B of the smoother).
     """
@@ -146,13 +217,20 @@ def element_jacobian(lev, tab, mat, U, phit, cells, couple=True):
     # sigma of every displacement trial function: (nq, k, d, d)
     sig_w = 2.0 * mat.mu * tab.eps_w + mat.lam * tab.div_w[..., None, None] * eye
     gq = mat.g(s["phit"])
-    K[:, :nu_, :nu_] = np.einsum("q,cq,qlij,qkij->ckl", tab.JxW, gq, sig_w, tab.eps_w)
+    if s["split"] is None:
+        K[:, :nu_, :nu_] = np.einsum("q,cq,qlij,qkij->ckl", tab.JxW, gq, sig_w, tab.eps_w)
+    else:
+        # C - (1 - g) C^+ applied to the strain of every trial function
+        h = np.broadcast_to(tab.eps_w[None], (nc,) + tab.eps_w.shape)
+        Cp = tangent_pos(mat, s["split"], h)                                # (nc, nq, k, d, d)
+        sig_t = sig_w[None] - (1.0 - gq)[..., None, None, None] * Cp
+        K[:, :nu_, :nu_] = np.einsum("q,cqlij,qkij->ckl", tab.JxW, sig_t, tab.eps_w)
     if couple:
-        sig_e = np.einsum("cqij,qlij->cql", s["sigma"], tab.eps_w)          # sigma(u):e(du)
+        sig_e = np.einsum("cqij,qlij->cql", s["sigma_pos"], tab.eps_w)      # sigma^+(u):e(du)
         coef = ES_FACTOR * mat.dg(s["phi"])[..., None] * sig_e \
             + 2.0 * p * s["phi"][..., None] * tab.div_w[None, :, :]
         K[:, nu_:, :nu_] = np.einsum("q,cql,qa->cal", tab.JxW, coef, tab.N)
-    cphi = ES_FACTOR * mat.d2g(s["phi"]) * s["Es"] + 2.0 * p * s["div_u"] + mat.G_c / mat.eps
+    cphi = ES_FACTOR * mat.d2g(s["phi"]) * s["Es_pos"] + 2.0 * p * s["div_u"] + mat.G_c / mat.eps
     K[:, nu_:, nu_:] = np.einsum("q,cq,qb,qa->cab", tab.JxW, cphi, tab.N, tab.N)
     K[:, nu_:, nu_:] += mat.G_c * mat.eps * np.einsum("q,qbj,qaj->ab", tab.JxW, tab.dN, tab.dN)[None]
     return K

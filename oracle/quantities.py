@@ -4,11 +4,11 @@ Quantities of interest of Sec. 5, evaluated cell by cell with the cell
 quadrature (p+1 Gauss points per direction), with the state U = (u, phi):
 
   crack energy  E_c = int G_c/2 ( (1 - phi)^2 / eps + eps grad phi . grad phi ) dx
-  bulk energy   E_b = int g_kappa(phi) E_s(e(u)) + phi^2 p div u dx
-                (no stress split: E_s^+ = E_s, E_s^- = 0)
+  bulk energy   E_b = int g_kappa(phi) E_s^+(e(u)) + E_s^-(e(u)) + phi^2 p div u dx
+                (no stress split: E_s^+ = E_s, E_s^- = 0; Miehe split as in model.py)
   boundary load L = int_Gamma sigma n ds over one face of the box,
-                with sigma = g_kappa(phi) sigma(u) (reading: the degraded stress of the
-                displacement equation, current phi), on the face's p+1 Gauss points
+                with sigma = g_kappa(phi) sigma^+(u) + sigma^-(u) (reading: the degraded
+                stress of the displacement equation, current phi), on the face's p+1 Gauss points
                 per tangential direction; faces of hole cells are not part of the box
                 face.
 """
@@ -17,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 
 from .fe import gauss_legendre_01, lagrange_1d, local_multi_indices
-from .model import CellTables, qp_state
+from .model import CellTables, miehe_split, qp_state
 
 
 def energies(lev, mat, U):
@@ -28,7 +28,8 @@ def energies(lev, mat, U):
     s = qp_state(lev, tab, mat, U, U[d * nn:], cells)   # phi~ slot unused here
     phi, gphi = s["phi"], s["grad_phi"]
     crack = 0.5 * mat.G_c * ((1.0 - phi) ** 2 / mat.eps + mat.eps * np.einsum("cqj,cqj->cq", gphi, gphi))
-    bulk = mat.g(phi) * s["Es"] + phi ** 2 * mat.pressure * s["div_u"]
+    # g E_s^+ + E_s^- = E_s - (1 - g) E_s^+
+    bulk = s["Es"] - (1.0 - mat.g(phi)) * s["Es_pos"] + phi ** 2 * mat.pressure * s["div_u"]
     return float(np.einsum("q,cq->", tab.JxW, crack)), float(np.einsum("q,cq->", tab.JxW, bulk))
 
 
@@ -74,5 +75,9 @@ def boundary_traction(lev, mat, U, face):
     e = 0.5 * (gu + np.swapaxes(gu, 2, 3))
     tr = np.trace(e, axis1=2, axis2=3)
     sig = 2.0 * mat.mu * e + mat.lam * tr[..., None, None] * np.eye(d)
-    t = np.einsum("cq,cqij,j->cqi", mat.g(phi), sig, n_vec)
+    if mat.split == "miehe":
+        sig = sig - (1.0 - mat.g(phi))[..., None, None] * miehe_split(mat, e)["sigma_pos"]
+    else:
+        sig = mat.g(phi)[..., None, None] * sig
+    t = np.einsum("cqij,j->cqi", sig, n_vec)
     return np.einsum("q,cqi->i", w, t)

@@ -39,7 +39,16 @@ def spec(name, dim, degree, n, n_levels, domain=BOX, faces=None, E=1.0, nu=0.3, 
 
 
 def config(name):
-    """The named workloads (sizes of the paper's test families, synthetic data)."""
+    """The named workloads (sizes of the paper's test families, synthetic data).
+
+    A name ending in "_miehe" is the named workload with the Miehe spectral split
+    (Sec. 2.1) in place of the unsplit energy: material["split"] = "miehe".
+    """
+    if name.endswith("_miehe"):
+        s = config(name[: -len("_miehe")])
+        s["name"] = name
+        s["material"] = dict(s["material"], split="miehe")
+        return s
     if name == "cfg1_2d_q1_32":
         # 2D unit square 32^2 Q1, crack segment of length 0.25 at the centre, 3 levels
         return spec(name, 2, 1, 32, 3, cracks=[("segment", (0.375, 0.5), (0.625, 0.5))])
