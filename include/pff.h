@@ -64,6 +64,15 @@ typedef int pf_status;
 #define PF_PREC_FULL 0
 #define PF_PREC_DIAG 1
 
+/* Energy split (Sec. 2.1): PF_SPLIT_NONE uses E_s^+ = E_s (the unsplit form); PF_SPLIT_MIEHE
+ * uses the spectral split E_s^+ = lam/2 <tr e>_+^2 + mu tr(e_+^2) with sigma^+ = dE_s^+/de,
+ * which makes the displacement equation nonlinear; its Jacobian is the consistent tangent
+ * (the derivative of e -> e_+ by the divided differences of <.>_+ at the eigenvalue pairs;
+ * d<x>_+/dx = 0 at x = 0, and an eigenvalue or tr e within 1e-13 of the spectral radius of
+ * zero counts as zero).  In 2D the split acts on the in-plane strain of plane strain. */
+#define PF_SPLIT_NONE 0
+#define PF_SPLIT_MIEHE 1
+
 #define PF_BOX 0
 #define PF_LSHAPE 1 /* [0,1]^3 minus [0.5,1]x[0.5,1]x[0,1] (2D: the same without z), scaled by extent */
 
@@ -103,6 +112,8 @@ typedef struct pf_options {
   double gmres_atol;       /* absolute floor of the FGMRES stop (default 0; the inexact solves of
                               Sec. 5 use rtol 1e-4 with a small floor) */
   int preconditioner;      /* PF_PREC_FULL (default, the paper's choice) or PF_PREC_DIAG */
+  int stress_split;        /* PF_SPLIT_NONE (default) or PF_SPLIT_MIEHE: the model's energy split
+                              (pf_setup only; the batched solver supports PF_SPLIT_NONE) */
 } pf_options;
 
 typedef struct pf_newton_report {

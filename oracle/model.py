@@ -28,7 +28,9 @@ Readings of the paper used here (also listed in the design notes):
   for E = 1e4, nu = 0.2);
 * split: the Heaviside step H = d<x>_+/dx is taken as 0 at x = 0 (a zero
   eigenvalue or trace counts as not in tension; at e = 0 the tangent is the
-  undegraded C), and in 2D the split acts on the in-plane 2x2 strain (the
+  undegraded C); an eigenvalue, or tr e, within SPLIT_SNAP times the spectral
+  radius of e of zero is taken as zero (its sign is rounding noise of the
+  eigensolver, and the tangent jumps there); in 2D the split acts on the in-plane 2x2 strain (the
   out-of-plane eigenvalue of plane strain is 0 and adds nothing to e_+, tr e,
   or the in-plane tangent).
 """
@@ -42,6 +44,7 @@ import scipy.sparse as sp
 from .fe import Level, gauss_lobatto_01, local_multi_indices
 
 ES_FACTOR = 0.5
+SPLIT_SNAP = 1e-13
 
 
 @dataclass
@@ -97,6 +100,9 @@ def miehe_split(mat: Material, e):
     d = e.shape[-1]
     lam_i, N = np.linalg.eigh(e)                       # ascending, eigenvectors in columns
     tr = np.trace(e, axis1=-2, axis2=-1)
+    rad = np.abs(lam_i).max(axis=-1)
+    lam_i = np.where(np.abs(lam_i) <= SPLIT_SNAP * rad[..., None], 0.0, lam_i)
+    tr = np.where(np.abs(tr) <= SPLIT_SNAP * rad, 0.0, tr)
     lp = positive_part(lam_i)
     e_pos = np.einsum("...ia,...a,...ja->...ij", N, lp, N)
     Es_pos = 0.5 * mat.lam * positive_part(tr) ** 2 + mat.mu * np.sum(lp * lp, axis=-1)

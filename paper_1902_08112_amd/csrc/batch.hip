@@ -564,7 +564,7 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
     bl.h_inst.resize(n);
     for (int b = 0; b < n; ++b) {
       const Geom g = inst_geom(meshes[b], l);
-      Material m = mats ? (*mats)[b] : Material{1, 1, 1, 1, 0, 0};
+      Material m = mats ? (*mats)[b] : Material{1, 1, 1, 1, 0, 0, PF_SPLIT_NONE};
       bl.h_inst[b].cp = make_cell_params(g, m);
       bl.h_inst[b].faces = meshes[b].dirichlet_faces;
       bl.h_inst[b].dof_off = bl.h_dof[b];
@@ -1164,6 +1164,10 @@ pf_status pf_batch_workspace_size(const pf_mesh* meshes, int n, const pf_options
   pf_default_options(&o);
   if (opt) o = *opt;
   PFF_TRY(validate_batch(meshes, nullptr, n, &o));
+  if (o.stress_split != PF_SPLIT_NONE) {
+    set_error("the batched solver supports stress_split = PF_SPLIT_NONE only");
+    return PF_ERR_UNSUPPORTED;
+  }
   for (int b = 0; b < n; ++b) {
     size_t tmp = 0;
     PFF_TRY(pf_workspace_size(&meshes[b], &o, &tmp));
@@ -1183,6 +1187,10 @@ pf_status pf_batch_setup(const pf_mesh* meshes, const double* materials, int n, 
   pf_default_options(&o);
   if (opt) o = *opt;
   PFF_TRY(validate_batch(meshes, materials, n, &o));
+  if (o.stress_split != PF_SPLIT_NONE) {
+    set_error("the batched solver supports stress_split = PF_SPLIT_NONE only");
+    return PF_ERR_UNSUPPORTED;
+  }
   for (int b = 0; b < n; ++b) {
     size_t tmp = 0;
     PFF_TRY(pf_workspace_size(&meshes[b], &o, &tmp));
@@ -1213,6 +1221,7 @@ pf_status pf_batch_setup(const pf_mesh* meshes, const double* materials, int n, 
     mm.eps = m[3];
     mm.kappa = m[4];
     mm.p = m[5];
+    mm.split = PF_SPLIT_NONE;
     c->mats.push_back(mm);
   }
   bcarve(c, meshes, n, o, reinterpret_cast<char*>(d_workspace), &c->mats);

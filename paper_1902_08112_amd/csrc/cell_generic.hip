@@ -4,12 +4,13 @@
 // Jacobian (Sec. 4.1), the residual -A(U) or the diagonal of G with the
 // integrands of generic_cell.h, and scatters with device atomics.  The Q1
 // kernels of cell_q1.hip are the fast path; this kernel covers Q2, the
-// residual and diagonal modes, and the unmasked (lift) apply.
+// residual and diagonal modes, the unmasked (lift) apply, and every mode of the
+// Miehe split (SPLIT: the split evaluated on the fly at each point).
 #include "generic_cell.h"
 
 namespace pff {
 
-template <int D, int P, typename T, int MODE>
+template <int D, int P, typename T, int MODE, bool SPLIT>
 __global__ __launch_bounds__(128) void k_cell_generic(CellParams cp, const T* __restrict__ x,
                                                       const T* __restrict__ U, const T* __restrict__ phit,
                                                       const uint8_t* __restrict__ mask, T* __restrict__ y) {
@@ -38,29 +39,32 @@ __global__ __launch_bounds__(128) void k_cell_generic(CellParams cp, const T* __
   }
   constexpr bool kDir = (MODE == MODE_APPLY || MODE == MODE_BLOCK || MODE == MODE_RAW);
   constexpr bool kMasked = (MODE == MODE_APPLY || MODE == MODE_BLOCK);
-  T xv[D + 1][NL];
-  T uv[D + 1][NL];
-  T pv[NL];
+  // arithmetic type: the split is evaluated in FP64 whatever the storage type T (FP32 levels
+  // read and write FP32 vectors)
+  using TC = typename std::conditional<SPLIT, double, T>::type;
+  TC xv[D + 1][NL];
+  TC uv[D + 1][NL];
+  TC pv[NL];
   uint8_t mk[NL];
 #pragma unroll
   for (int a = 0; a < NL; ++a) {
     mk[a] = kMasked ? mask[g[a]] : 0;
-    pv[a] = phit[g[a]];
+    pv[a] = (TC)phit[g[a]];
 #pragma unroll
     for (int i = 0; i <= D; ++i) {
-      uv[i][a] = U[i * nn + g[a]];
-      T v = kDir ? x[i * nn + g[a]] : T(0);
-      xv[i][a] = (kMasked && (mk[a] & mask_bit(i, D))) ? T(0) : v;
+      uv[i][a] = (TC)U[i * nn + g[a]];
+      TC v = kDir ? (TC)x[i * nn + g[a]] : TC(0);
+      xv[i][a] = (kMasked && (mk[a] & mask_bit(i, D))) ? TC(0) : v;
     }
   }
-  T out[D + 1][NL];
-  generic_cell<D, P, T, MODE>(cp, xv, uv, pv, out);
+  TC out[D + 1][NL];
+  generic_cell<D, P, TC, MODE, SPLIT>(cp, xv, uv, pv, out);
 #pragma unroll
   for (int a = 0; a < NL; ++a)
 #pragma unroll
     for (int i = 0; i <= D; ++i) {
       if (kMasked && (mk[a] & mask_bit(i, D))) continue;
-      atomicAdd(&y[i * nn + g[a]], out[i][a]);
+      atomicAdd(&y[i * nn + g[a]], (T)out[i][a]);
     }
 }
 
@@ -87,30 +91,31 @@ CellParams make_cell_params(const Geom& g, const Material& m) {
   cp.zc = -1;
   cp.d = g.d;
   cp.p = g.p;
+  cp.split = m.split;
   return cp;
 }
 
-template <int D, int P, typename T>
-static pf_status launch_dp(const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
-                           const uint8_t* mask, T* y, hipStream_t s) {
+template <int D, int P, typename T, bool SPLIT>
+static pf_status launch_dps(const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                            const uint8_t* mask, T* y, hipStream_t s) {
   const int bs = 128;
   const int64_t nb = (cp.n_cells + bs - 1) / bs;
   if (nb == 0) return PF_OK;
   switch (mode) {
     case MODE_APPLY:
-      k_cell_generic<D, P, T, MODE_APPLY><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
+      k_cell_generic<D, P, T, MODE_APPLY, SPLIT><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
       break;
     case MODE_BLOCK:
-      k_cell_generic<D, P, T, MODE_BLOCK><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
+      k_cell_generic<D, P, T, MODE_BLOCK, SPLIT><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
       break;
     default:
       if constexpr (std::is_same<T, double>::value) {
         if (mode == MODE_RAW)
-          k_cell_generic<D, P, T, MODE_RAW><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
+          k_cell_generic<D, P, T, MODE_RAW, SPLIT><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
         else if (mode == MODE_RESID)
-          k_cell_generic<D, P, T, MODE_RESID><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
+          k_cell_generic<D, P, T, MODE_RESID, SPLIT><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
         else if (mode == MODE_DIAG)
-          k_cell_generic<D, P, T, MODE_DIAG><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
+          k_cell_generic<D, P, T, MODE_DIAG, SPLIT><<<nb, bs, 0, s>>>(cp, x, U, phit, mask, y);
         else {
           set_error("unknown cell mode");
           return PF_ERR_INVALID_ARG;
@@ -122,6 +127,13 @@ static pf_status launch_dp(const CellParams& cp, int mode, const T* x, const T* 
   }
   PFF_CHECK_LAUNCH();
   return PF_OK;
+}
+
+template <int D, int P, typename T>
+static pf_status launch_dp(const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                           const uint8_t* mask, T* y, hipStream_t s) {
+  return cp.split ? launch_dps<D, P, T, true>(cp, mode, x, U, phit, mask, y, s)
+                  : launch_dps<D, P, T, false>(cp, mode, x, U, phit, mask, y, s);
 }
 
 pf_status launch_cell_generic_d(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,

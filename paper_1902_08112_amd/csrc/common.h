@@ -72,11 +72,13 @@ struct CellParams {
   int variant;         // Q1 cell-loop variant (-1: size heuristic), see cell_q1.hip
   int zc;              // node planes per marching chunk (<= 0: heuristic)
   int d, p;            // dimension and degree
+  int split;           // PF_SPLIT_NONE or PF_SPLIT_MIEHE (Sec. 2.1)
 };
 
-// Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p.
+// Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p; energy split.
 struct Material {
   double mu, lam, Gc, eps, kappa, p;
+  int split;
 };
 
 CellParams make_cell_params(const Geom& g, const Material& m);

@@ -1,15 +1,19 @@
 // Per-cell operator math for any (dim, degree) by direct evaluation at the
 // (p+1)^d Gauss points: Jacobian (full or smoother block), residual -A(U),
-// or the diagonal of G.  Integrands of the semi-linear form (Sec. 2.3, no
-// split, phi~ in the displacement equation, the 1/2 of the phase-field
-// equation read literally):
+// or the diagonal of G.  Integrands of the semi-linear form (Sec. 2.3, phi~ in
+// the displacement equation, the 1/2 of the phase-field equation read literally):
 //   u rows:   g(phi~) sigma(du) : e(w)                     [residual: + phi~^2 p div w]
 //   phi rows: [(1-kappa) phi sigma(u):e(du) + 2 p phi div du
 //              + ((1-kappa) E_s(e(u)) + 2 p div u + G_c/eps) dphi] psi
 //             + G_c eps grad dphi . grad psi
+// With SPLIT (Miehe split, Sec. 2.1, split.h) E_s and sigma(u) of the phase-field rows
+// become E_s^+ and sigma^+(u), and the displacement rows use g sigma^+ + sigma^- =
+// sigma - (1 - g) sigma^+ with the tangent C - (1 - g) C^+ at e(u); the split at each
+// point is evaluated on the fly in FP64.
 #pragma once
 
 #include "common.h"
+#include "split.h"
 
 namespace pff {
 
@@ -69,7 +73,7 @@ struct Tens {
 };
 
 // out[i][a] = contributions of one cell; xv: direction (already masked), uv: U, pv: phi~
-template <int D, int P, typename T, int MODE>
+template <int D, int P, typename T, int MODE, bool SPLIT = false>
 __device__ __forceinline__ void generic_cell(const CellParams& cp, const T (&xv)[D + 1][Tens<D, P>::NL],
                                              const T (&uv)[D + 1][Tens<D, P>::NL], const T (&pv)[Tens<D, P>::NL],
                                              T (&out)[D + 1][Tens<D, P>::NL]) {
@@ -122,9 +126,32 @@ __device__ __forceinline__ void generic_cell(const CellParams& cp, const T (&xv)
       }
     const T Es = T(0.5) * lam * tr_u * tr_u + mu * ee;
     const T gdeg = (T(1) - kap) * pt * pt + kap;
+    const T omg = T(1) - gdeg;  // 1 - g(phi~)
+    // E_s^+ and sigma^+(u): the split at this point, or E_s and sigma(u) without one
+    split::QP<D> sq;
+    T EsP = Es;
+    T sp[D][D];
+    if constexpr (SPLIT) {
+      double ed[D][D];
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) ed[i][j] = 0.5 * ((double)gu[i][j] + (double)gu[j][i]);
+      split::eval<D>(ed, cp.mu, cp.lam, sq);
+      EsP = T(sq.Es_pos);
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) sp[i][j] = T(sq.sig[i][j]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) sp[i][j] = su[i][j];
+    }
 
     if (MODE == MODE_DIAG) {
-      const T cphi = (T(1) - kap) * Es + T(2) * pres * tr_u + gce;
+      const T cphi = (T(1) - kap) * EsP + T(2) * pres * tr_u + gce;
 #pragma unroll
       for (int a = 0; a < NL; ++a) {
         const T Na = T(TT::N(q, a));
@@ -135,8 +162,17 @@ __device__ __forceinline__ void generic_cell(const CellParams& cp, const T (&xv)
           dn[j] = T(TT::dN(q, a, j)) * ih[j];
           g2 += dn[j] * dn[j];
         }
+        double dnd[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) out[i][a] += jxw * gdeg * (mu * (g2 + dn[i] * dn[i]) + lam * dn[i] * dn[i]);
+        for (int j = 0; j < D; ++j) dnd[j] = (double)dn[j];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          const T ece = mu * (g2 + dn[i] * dn[i]) + lam * dn[i] * dn[i];  // e(w):C e(w), w = N_a e_i
+          if constexpr (SPLIT)
+            out[i][a] += jxw * (ece - omg * T(split::test_energy<D>(sq, cp.mu, cp.lam, i, dnd)));
+          else
+            out[i][a] += jxw * gdeg * ece;
+        }
         out[D][a] += jxw * (cphi * Na * Na + gcx * g2);
       }
       continue;
@@ -148,8 +184,11 @@ __device__ __forceinline__ void generic_cell(const CellParams& cp, const T (&xv)
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
-        for (int j = 0; j < D; ++j) tau[i][j] = -(gdeg * su[i][j] + (i == j ? pt * pt * pres : T(0)));
-      fval = -((T(1) - kap) * phi * Es + T(2) * phi * pres * tr_u - gce * (T(1) - phi));
+        for (int j = 0; j < D; ++j) {
+          const T sg = SPLIT ? su[i][j] - omg * sp[i][j] : gdeg * su[i][j];
+          tau[i][j] = -(sg + (i == j ? pt * pt * pres : T(0)));
+        }
+      fval = -((T(1) - kap) * phi * EsP + T(2) * phi * pres * tr_u - gce * (T(1) - phi));
 #pragma unroll
       for (int j = 0; j < D; ++j) zeta[j] = -gcx * gphi[j];
     } else {
@@ -176,15 +215,29 @@ __device__ __forceinline__ void generic_cell(const CellParams& cp, const T (&xv)
       T tr_d = T(0), se = T(0);
 #pragma unroll
       for (int i = 0; i < D; ++i) tr_d += gd[i][i];
+      double hd[D][D], cpd[D][D];
 #pragma unroll
       for (int i = 0; i < D; ++i)
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           const T e = T(0.5) * (gd[i][j] + gd[j][i]);
-          se += su[i][j] * e;
-          tau[i][j] = gdeg * (T(2) * mu * e + (i == j ? lam * tr_d : T(0)));
+          se += sp[i][j] * e;
+          tau[i][j] = T(2) * mu * e + (i == j ? lam * tr_d : T(0));
+          hd[i][j] = (double)e;
         }
-      const T cphi = (T(1) - kap) * Es + T(2) * pres * tr_u + gce;
+      if constexpr (SPLIT) {
+        split::tangent<D>(sq, cp.mu, cp.lam, hd, cpd);  // C^+ e(du)
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) tau[i][j] -= omg * T(cpd[i][j]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) tau[i][j] *= gdeg;
+      }
+      const T cphi = (T(1) - kap) * EsP + T(2) * pres * tr_u + gce;
       fval = cphi * dphi;
       if (MODE != MODE_BLOCK) fval += (T(1) - kap) * phi * se + T(2) * pres * phi * tr_d;
 #pragma unroll

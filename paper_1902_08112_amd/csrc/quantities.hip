@@ -1,8 +1,9 @@
 // Quantities of interest of Sec. 5 as fused reductions over the cells of the
 // finest level, state U = (u, phi):
 //   crack energy  E_c = int G_c/2 ((1 - phi)^2 / eps + eps |grad phi|^2)
-//   bulk energy   E_b = int g_kappa(phi) E_s(e(u)) + phi^2 p div u   (no split)
-//   face load     L = int_face g_kappa(phi) sigma(u) n ds on one box face
+//   bulk energy   E_b = int g_kappa(phi) E_s^+(e(u)) + E_s^-(e(u)) + phi^2 p div u
+//   face load     L = int_face (g_kappa(phi) sigma^+(u) + sigma^-(u)) n ds on one box face
+// (without a split E_s^+ = E_s, sigma^+ = sigma; with the Miehe split the parts of split.h)
 // evaluated at the cell's (p+1)^d Gauss points (the facet's (p+1)^(d-1)).
 // One thread per cell; per-block partial sums in a fixed grid, then one final
 // block, so the sums are deterministic.
@@ -95,8 +96,21 @@ __global__ __launch_bounds__(kQBlock) void k_energies(CellParams cp, double Gc, 
         }
       }
       const double Es = 0.5 * lam * tr * tr + mu * ee;
+      const double gd = (1.0 - kap) * phi * phi + kap;
       ec += jxw * 0.5 * Gc * ((1.0 - phi) * (1.0 - phi) / eps + eps * g2);
-      eb += jxw * (((1.0 - kap) * phi * phi + kap) * Es + phi * phi * pres * tr);
+      if (cp.split) {
+        // g E_s^+ + E_s^- = E_s - (1 - g) E_s^+
+        double ed[D][D];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) ed[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
+        split::QP<D> sq;
+        split::eval<D>(ed, mu, lam, sq);
+        eb += jxw * (Es - (1.0 - gd) * sq.Es_pos + phi * phi * pres * tr);
+      } else {
+        eb += jxw * (gd * Es + phi * phi * pres * tr);
+      }
     }
   }
   const double bc = qsum(ec, sh);
@@ -185,11 +199,26 @@ __global__ __launch_bounds__(kQBlock) void k_face_traction(CellParams cp, int fa
 #pragma unroll
       for (int i = 0; i < D; ++i) tr += gu[i][i];
       const double gd = (1.0 - kap) * phi * phi + kap;
-      // (sigma n)_i = sigma_ik * nsign
+      // (sigma n)_i = sigma_ik * nsign; with the split sigma - (1 - g) sigma^+
+      if (cp.split) {
+        double ed[D][D];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const double sik = mu * (gu[i][k] + gu[k][i]) + (i == k ? lam * tr : 0.0);
-        acc[i] += w * gd * sik * nsign;
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+          for (int j = 0; j < D; ++j) ed[i][j] = 0.5 * (gu[i][j] + gu[j][i]);
+        split::QP<D> sq;
+        split::eval<D>(ed, mu, lam, sq);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          const double sik = mu * (gu[i][k] + gu[k][i]) + (i == k ? lam * tr : 0.0);
+          acc[i] += w * (sik - (1.0 - gd) * sq.sig[i][k]) * nsign;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          const double sik = mu * (gu[i][k] + gu[k][i]) + (i == k ? lam * tr : 0.0);
+          acc[i] += w * gd * sik * nsign;
+        }
       }
     }
   }

@@ -39,6 +39,7 @@ pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, i
 template <>
 pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
                               const double* phit, const uint8_t* mask, double* y, hipStream_t s) {
+  if (cp.split) return launch_cell_generic_d(g, cp, mode, x, U, phit, mask, y, s);
   bool handled = false;
   pf_status st = launch_cell_q1_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
@@ -49,6 +50,7 @@ pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, con
 template <>
 pf_status launch_cell<float>(const Geom& g, const CellParams& cp, int mode, const float* x, const float* U,
                              const float* phit, const uint8_t* mask, float* y, hipStream_t s) {
+  if (cp.split) return launch_cell_generic_f(g, cp, mode, x, U, phit, mask, y, s);
   bool handled = false;
   pf_status st = launch_cell_q1_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
@@ -60,11 +62,16 @@ pf_status launch_cell<float>(const Geom& g, const CellParams& cp, int mode, cons
 // modes whose output starts from Pi_C x (identity rows on constrained DoFs)
 static bool starts_from_constrained(int mode) { return mode == MODE_APPLY || mode == MODE_BLOCK; }
 
+// the cell loop for (cp, mode) is a tiled Q1 kernel, which writes every entry of y itself
+static bool tiled_writes_all(const Geom& g, const CellParams& cp, int mode) {
+  return !cp.split && q1_tiled_handles(g, mode, cp.variant);
+}
+
 // overwrite y with the operator result on one level's data
 template <typename T>
 pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                    const uint8_t* mask, T* y, hipStream_t s, bool y_preset = false) {
-  if (q1_tiled_handles(g, mode, cp.variant)) {
+  if (tiled_writes_all(g, cp, mode)) {
     // the tiled kernels write every entry, identity rows included
   } else if (starts_from_constrained(mode)) {
     // y = Pi_C x, unless the producer of x already wrote it
@@ -304,6 +311,10 @@ pf_status validate_opts(const pf_options* o) {
     set_error("preconditioner must be PF_PREC_FULL or PF_PREC_DIAG");
     return PF_ERR_INVALID_ARG;
   }
+  if (o->stress_split != PF_SPLIT_NONE && o->stress_split != PF_SPLIT_MIEHE) {
+    set_error("stress_split must be PF_SPLIT_NONE or PF_SPLIT_MIEHE");
+    return PF_ERR_INVALID_ARG;
+  }
   return PF_OK;
 }
 
@@ -428,7 +439,7 @@ CellParams level_params(pf_ctx* c, int l, int prec, int mode) {
 // whether the (level, prec, mode) operator starts from y = Pi_C x written by a separate pass
 bool apply_needs_preset(pf_ctx* c, int l, int prec, int mode) {
   const CellParams cp = level_params(c, l, prec, mode);
-  return !q1_tiled_handles(c->lev[l].g, mode, cp.variant);
+  return !tiled_writes_all(c->lev[l].g, cp, mode);
 }
 
 // y_preset: the caller already stored y = Pi_C x (fused into the kernel that produced x)
@@ -439,7 +450,7 @@ pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void*
   if (c->ktime_on && prec == PF_F64 && mode == MODE_APPLY && l == (int)c->lev.size() - 1 &&
       c->ktime_n < kKernelTimerMax) {
     // the Pi_C start (when needed) outside, the cell kernel alone between the two events
-    if (!y_preset && !q1_tiled_handles(b.g, mode, cp.variant))
+    if (!y_preset && !tiled_writes_all(b.g, cp, mode))
       PFF_TRY(vec_init_constrained<double>((double*)y, (const double*)x, b.mask, b.g.n_nodes, b.g.d, s));
     hipEvent_t* ev = &c->ktime_ev[2 * c->ktime_n++];
     PFF_HIP(hipEventRecord(ev[0], s));
@@ -532,7 +543,7 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
   const pf_options& o = c->opt;
   const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
   const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
-  if (c->fused_coarse) {
+  if (c->fused_coarse && !c->mat.split) {
     const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
     bool handled = false;
     PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
@@ -888,6 +899,7 @@ void pf_default_options(pf_options* o) {
   o->pdas_c = 100.0;
   o->eig_seed = 12345;
   o->preconditioner = PF_PREC_FULL;
+  o->stress_split = PF_SPLIT_NONE;
 }
 
 const char* pf_status_string(pf_status s) {
@@ -955,6 +967,7 @@ pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double 
   c->mat.eps = eps;
   c->mat.kappa = kappa;
   c->mat.p = pressure;
+  c->mat.split = o.stress_split;
   c->ws_bytes = ws_bytes;
   carve(c, *mesh, o, reinterpret_cast<char*>(d_workspace));
   hipStream_t s = st(stream);
@@ -1445,7 +1458,7 @@ static const int kNCand = 12;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];
-  if (b.g.p != 1) return PF_OK;
+  if (b.g.p != 1 || c->mat.split) return PF_OK;  // the split runs the generic cell loop
   hipEvent_t e0, e1;
   PFF_HIP(hipEventCreate(&e0));
   PFF_HIP(hipEventCreate(&e1));

@@ -20,6 +20,7 @@ PF_OK, PF_ERR_INVALID_ARG, PF_ERR_UNSUPPORTED, PF_ERR_DEVICE = 0, 1, 2, 3
 PF_ERR_WORKSPACE, PF_ERR_NOT_CONVERGED, PF_ERR_NONFINITE = 4, 5, 6
 PF_F64, PF_F32 = 0, 1
 PF_PREC_FULL, PF_PREC_DIAG = 0, 1
+PF_SPLIT_NONE, PF_SPLIT_MIEHE = 0, 1
 PF_BOX, PF_LSHAPE = 0, 1
 PF_MASK_PHI = 8
 
@@ -40,7 +41,8 @@ class Options(C.Structure):
                 ("cheb_safety", C.c_double), ("eig_cg_steps", C.c_int), ("coarse_degree", C.c_int),
                 ("coarse_sweeps", C.c_int), ("coarse_lo_factor", C.c_double), ("gmres_restart", C.c_int),
                 ("gmres_max_iter", C.c_int), ("gmres_rtol", C.c_double), ("pdas_c", C.c_double),
-                ("eig_seed", C.c_uint64), ("gmres_atol", C.c_double), ("preconditioner", C.c_int)]
+                ("eig_seed", C.c_uint64), ("gmres_atol", C.c_double), ("preconditioner", C.c_int),
+                ("stress_split", C.c_int)]
 
 
 class NewtonReport(C.Structure):
@@ -333,7 +335,9 @@ class Solver:
         import torch
         self.torch = torch
         self.mesh = mesh
-        self.opt = opt or pf_default_options()
+        self.opt = Options.from_buffer_copy(opt) if opt is not None else pf_default_options()
+        if "split" in material:   # the model's energy split comes with the material
+            self.opt.stress_split = {"none": PF_SPLIT_NONE, "miehe": PF_SPLIT_MIEHE}[material["split"]]
         self.ws_bytes = pf_workspace_size(mesh, self.opt)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
         base = self.ws.data_ptr()

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
     assert o.cheb_degree == 4 and abs(o.cheb_ratio - 5) < 1e-15 and abs(o.cheb_safety - 1.2) < 1e-15
     assert o.eig_cg_steps == 10 and o.coarse_degree == 20 and abs(o.coarse_lo_factor - 0.9) < 1e-15
     assert abs(o.pdas_c - 100) < 1e-15 and o.gmres_restart == 50 and abs(o.gmres_rtol - 1e-8) < 1e-20
-    assert o.gmres_atol == 0.0 and o.preconditioner == pff.PF_PREC_FULL
+    assert o.gmres_atol == 0.0 and o.preconditioner == pff.PF_PREC_FULL and o.stress_split == pff.PF_SPLIT_NONE
 
 
 @pytest.mark.parametrize("field,value,code", [("dim", 4, 2), ("degree", 3, 2), ("n_levels", 0, 1),
@@ -86,7 +86,7 @@ def test_options_validation():
     m = pff.make_mesh(2, 1, (8, 8), (1, 1), 0, 2, 15)
     for field, value in [("vcycle_precision", 3), ("cheb_degree", 0), ("cheb_ratio", 1.0), ("eig_cg_steps", 0),
                          ("gmres_restart", 0), ("gmres_rtol", 0.0), ("pdas_c", float("inf")),
-                         ("gmres_atol", -1.0), ("preconditioner", 2)]:
+                         ("gmres_atol", -1.0), ("preconditioner", 2), ("stress_split", 2)]:
         o = pff.pf_default_options()
         setattr(o, field, value)
         with pytest.raises(pff.PffError):

@@ -1,0 +1,150 @@
+"""The Miehe spectral split (Sec. 2.1) on the GPU vs the oracle's split.
+
+Same bars as the unsplit operators: FP64 applies, block applies, residuals and diagonals
+to 1e-12 relative on every level, FP32 applies to 2e-6, the FP64 V-cycle to 1e-11, the
+FP32-level cycle to 1e-4, energies and face loads to 1e-12.  Newton steps solved to 1e-8
+on both sides agree to 1e-5; the PDAS loop (tight solves) takes the same number of
+corrections and ends at the same active set, |U - U_oracle| <= 1e-7 |U|.  Each case also
+checks that the split changes the operator (the states are not all-tension or
+all-compression, where the split and the unsplit forms coincide).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, oracle_hierarchy, rel_err
+from oracle import model, pdas, quantities
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["tiny2d_miehe", "tiny2d_q2_miehe", "tiny3d_miehe", "tiny3d_q2_miehe", "small3d_miehe",
+         "small_lshape_miehe", "cfg1_2d_q1_32_miehe"]
+
+
+def setup_case(name, seed=1, active_frac=0.1):
+    print(f"[case] split {name} seed={seed}", flush=True)
+    s = W.config(name)
+    U, phit = W.random_linearization(s, seed)
+    act = W.random_active(s, seed + 1, active_frac)
+    H = oracle_hierarchy(s)
+    H.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+    S = gpu_solver(s)
+    S.set_linearization(dev(U), dev(phit), dev(act))
+    return s, U, phit, act, H, S
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_split_apply_all_levels(name):
+    s, U, phit, act, H, S = setup_case(name)
+    torch = __import__("torch")
+    plain = model.Material(**dict(s["material"], split="none"))
+    for l in range(s["n_levels"]):
+        lev = H.levels[l]
+        x = np.random.default_rng(100 + l).uniform(-1, 1, lev.n_dofs)
+        ref, refB = H.mg[l].G @ x, H.mg[l].B @ x
+        y = host(S.jacobian_apply(l, dev(x)))
+        yb = host(S.block_apply(l, dev(x)))
+        y32 = host(S.jacobian_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+        e, eb, e32 = rel_err(y, ref), rel_err(yb, refB), rel_err(y32, ref)
+        be = block_rel_errs(y, ref, lev.n_nodes, s["dim"])
+        print(f"  level {l}: rel {e:.2e} block {eb:.2e} FP32 {e32:.2e} per block {be}", flush=True)
+        assert e <= 1e-12 and eb <= 1e-12 and max(be.values()) <= 1e-12 and e32 <= 2e-6
+        c = H.mg[l].constrained
+        assert np.array_equal(y[c], x[c])
+    # the split is active on this state
+    G0 = model.constrain_matrix(model.assemble_jacobian(H.fine, plain, H.mg[-1].U, H.mg[-1].phit),
+                                H.mg[-1].constrained)
+    assert rel_err(G0 @ x, ref) > 1e-4
+
+
+@pytest.mark.parametrize("name", ["tiny2d_miehe", "tiny3d_q2_miehe", "small3d_miehe", "small_lshape_miehe"])
+def test_split_residual_and_diagonal(name):
+    s, U, phit, act, H, S = setup_case(name, seed=11)
+    fine = H.fine
+    ref = -model.assemble_residual(fine, H.mat, U, phit)
+    R = host(S.residual(dev(U), dev(phit)))
+    e = rel_err(R, ref)
+    print(f"  residual rel {e:.2e}", flush=True)
+    assert e <= 1e-12 and max(block_rel_errs(R, ref, fine.n_nodes, s["dim"]).values()) <= 1e-12
+    for l in range(s["n_levels"]):
+        ed = rel_err(host(S.diagonal(l)), H.mg[l].D)
+        print(f"  level {l}: diagonal rel {ed:.2e}", flush=True)
+        assert ed <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["small2d_miehe", "tiny3d_q2_miehe", "small3d_miehe", "small_lshape_miehe"])
+def test_split_vcycle_matches_oracle(name):
+    from paper_1902_08112_amd import PF_F32
+    s, U, phit, act, H, S = setup_case(name, seed=19)
+    bounds = []
+    for l in range(s["n_levels"]):
+        b = S.eig_bounds(l)
+        bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
+    H.set_linearization(U, phit, act, eig_bounds=bounds)
+    r = np.random.default_rng(23).uniform(-1, 1, H.fine.n_dofs)
+    z_ref = H.vcycle(r)
+    e = rel_err(host(S.vcycle(dev(r))), z_ref)
+    e32 = rel_err(host(S.vcycle(dev(r), PF_F32)), z_ref)
+    print(f"  vcycle rel {e:.2e}, FP32 levels {e32:.2e}", flush=True)
+    assert e <= 1e-11 and e32 <= 1e-4
+
+
+@pytest.mark.parametrize("name,prec", [("cfg1_2d_q1_32_miehe", "f64"), ("small3d_miehe", "f32"),
+                                       ("small_lshape_miehe", "f32"), ("tiny3d_q2_miehe", "f64")])
+def test_split_newton_step_matches_oracle(name, prec):
+    from oracle import newton
+    print(f"[case] split newton {name} {prec}", flush=True)
+    s = dict(W.config(name))
+    s["vcycle"] = prec
+    U, Uold, phit = W.make_state(s)
+    H = oracle_hierarchy(s)
+    ref = newton.newton_step(H, U, Uold, phit)
+    S = gpu_solver(s)
+    Ud = dev(U)
+    _, rep = S.newton_step(Ud, dev(Uold), dev(phit))
+    e = rel_err(host(Ud) - U, ref["dU"])
+    print(f"  gmres {rep.gmres_iters} (oracle {ref['info']['iters']}), rel res {rep.rel_residual:.2e}, "
+          f"|A| {rep.n_active} (oracle {ref['n_active']}), rel {e:.2e}", flush=True)
+    assert rep.converged and rep.rel_residual <= 1e-8
+    assert rep.n_active == ref["n_active"]
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["small2d_miehe", "tiny3d_miehe"])
+def test_split_pdas_loop_matches_oracle(name):
+    from paper_1902_08112_amd import pff
+    s = W.config(name)
+    print(f"[case] split pdas loop {name}", flush=True)
+    U0, Uold, phit = W.make_state(s)
+    H = oracle_hierarchy(s)
+    H.opts.gmres_rtol = 1e-12
+    ref = pdas.pdas_solve(H, U0, Uold, phit, tol_as=1e-10, max_iter=30)
+    S = gpu_solver(s, gmres_rtol=1e-12, vcycle_precision=pff.PF_F64)
+    U = dev(U0)
+    _, rep = S.pdas_solve(U, dev(Uold), dev(phit), max_iter=30, tol_as=1e-10)
+    print(f"  oracle {ref['iterations']} corrections, GPU {rep.iterations} ({rep.gmres_iters_total} FGMRES its), "
+          f"|R~| {rep.residual_norm:.1e}", flush=True)
+    assert ref["converged"] and rep.converged == 1
+    assert rep.iterations == ref["iterations"]
+    assert rep.n_active == int(ref["active"].sum())
+    assert rel_err(host(U), ref["U"]) <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["small2d_miehe", "tiny2d_q2_miehe", "small3d_miehe", "small_lshape_miehe"])
+def test_split_quantities_match_oracle(name):
+    s = W.config(name)
+    print(f"[case] split quantities {name}", flush=True)
+    mat = model.Material(**s["material"])
+    H = oracle_hierarchy(s)
+    S = gpu_solver(s)
+    for U in (W.make_state(s)[0], W.random_linearization(s, 41)[0]):
+        dU = dev(U)
+        ec, eb = S.energies(dU)
+        rc, rb = quantities.energies(H.fine, mat, U)
+        print(f"  energies GPU ({ec:.12e}, {eb:.12e}) oracle ({rc:.12e}, {rb:.12e})", flush=True)
+        assert abs(ec - rc) <= 1e-12 * abs(rc) and abs(eb - rb) <= 1e-12 * abs(rb)
+        ref = [quantities.boundary_traction(H.fine, mat, U, f) for f in range(2 * s["dim"])]
+        scale = max(np.abs(r).max() for r in ref)
+        for f in range(2 * s["dim"]):
+            t = np.array(S.boundary_traction(dU, f))
+            assert np.abs(t - ref[f]).max() <= 1e-12 * scale, (f, t, ref[f])

@@ -113,6 +113,20 @@ def test_split_tangent_at_zero_strain_and_plane_strain_embedding():
     # reading: H(0) = 0, so zero strain counts as not in tension
     sp = model.miehe_split(m, np.zeros((3, 3)))
     assert sp["Es_pos"] == 0.0 and np.abs(model.tangent_pos(m, sp, np.stack(sym_basis(3)))).max() == 0.0
+    # a rank-deficient strain (pure shear in a rotated frame): its zero eigenvalue comes out of
+    # the eigensolver as rounding noise of either sign; the snap makes it 0, and the tangent is
+    # the one of the exact zero eigenvalue (H(0) = 0)
+    rng = np.random.default_rng(4)
+    Q = rand_rot(rng, 3)
+    ex = np.array([[0.0, 0.3, 0.0], [0.3, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    e = Q @ ex @ Q.T
+    sp = model.miehe_split(m, e)
+    assert np.sort(sp["lam"])[1] == 0.0 and sp["tr"] == 0.0 and sp["H_tr"] == 0.0
+    sx = model.miehe_split(m, ex)
+    assert np.sort(sx["lam"])[1] == 0.0
+    for h in sym_basis(3):
+        assert np.allclose(model.tangent_pos(m, sp, h[None])[0],
+                           Q @ model.tangent_pos(m, sx, (Q.T @ h @ Q)[None])[0] @ Q.T, atol=1e-14)
     rng = np.random.default_rng(3)
     for eig in EIGS[2]:
         e2 = rand_strain(rng, 2, eig)
