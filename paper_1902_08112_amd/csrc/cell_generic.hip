@@ -92,6 +92,7 @@ CellParams make_cell_params(const Geom& g, const Material& m) {
   cp.d = g.d;
   cp.p = g.p;
   cp.split = m.split;
+  cp.qpd = nullptr;
   return cp;
 }
 

@@ -73,6 +73,7 @@ struct CellParams {
   int zc;              // node planes per marching chunk (<= 0: heuristic)
   int d, p;            // dimension and degree
   int split;           // PF_SPLIT_NONE or PF_SPLIT_MIEHE (Sec. 2.1)
+  const void* qpd;     // split: the level's per-point eigen-records in the apply's precision (or null)
 };
 
 // Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p; energy split.
@@ -101,6 +102,12 @@ enum CellMode {
 template <typename T>
 pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                       const uint8_t* mask, T* y, hipStream_t s);
+
+// Miehe split on Q1 levels (cell_split.hip): records of the per-point eigen-data
+// (split_record_values(d) values per cell), computed from the level's U
+int split_record_values(int d);
+pf_status launch_split_data(const Geom& g, const CellParams& cp, const double* U, double* rec64, float* rec32,
+                            hipStream_t s);
 
 // Q1 cell-loop variants: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles (both
 // write every node of y themselves), 2 = one thread per cell with atomics (y pre-set),

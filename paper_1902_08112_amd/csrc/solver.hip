@@ -19,6 +19,10 @@ pf_status launch_cell_generic_d(const Geom&, const CellParams&, int, const doubl
                                 const uint8_t*, double*, hipStream_t);
 pf_status launch_cell_generic_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
                                 const uint8_t*, float*, hipStream_t);
+pf_status launch_cell_q1s_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
+                            const uint8_t*, double*, hipStream_t, bool*);
+pf_status launch_cell_q1s_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
+                            const uint8_t*, float*, hipStream_t, bool*);
 pf_status launch_cell_q1_d(const Geom&, const CellParams&, int, const double*, const double*, const double*,
                            const uint8_t*, double*, hipStream_t, bool* handled);
 pf_status launch_cell_q1_f(const Geom&, const CellParams&, int, const float*, const float*, const float*,
@@ -39,8 +43,13 @@ pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, i
 template <>
 pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
                               const double* phit, const uint8_t* mask, double* y, hipStream_t s) {
-  if (cp.split) return launch_cell_generic_d(g, cp, mode, x, U, phit, mask, y, s);
   bool handled = false;
+  if (cp.split) {
+    // Q1 apply modes from the stored eigen-records, everything else on the fly
+    const pf_status sq = launch_cell_q1s_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
+    if (handled) return sq;
+    return launch_cell_generic_d(g, cp, mode, x, U, phit, mask, y, s);
+  }
   pf_status st = launch_cell_q1_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
   st = launch_cell_q2_d(g, cp, mode, x, U, phit, mask, y, s, &handled);
@@ -50,8 +59,12 @@ pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, con
 template <>
 pf_status launch_cell<float>(const Geom& g, const CellParams& cp, int mode, const float* x, const float* U,
                              const float* phit, const uint8_t* mask, float* y, hipStream_t s) {
-  if (cp.split) return launch_cell_generic_f(g, cp, mode, x, U, phit, mask, y, s);
   bool handled = false;
+  if (cp.split) {
+    const pf_status sq = launch_cell_q1s_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
+    if (handled) return sq;
+    return launch_cell_generic_f(g, cp, mode, x, U, phit, mask, y, s);
+  }
   pf_status st = launch_cell_q1_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
   if (handled) return st;
   st = launch_cell_q2_f(g, cp, mode, x, U, phit, mask, y, s, &handled);
@@ -147,6 +160,8 @@ struct LevelBuf {
   Geom g;
   double *U = nullptr, *phit = nullptr, *diag = nullptr;
   float *U32 = nullptr, *phit32 = nullptr, *diag32 = nullptr;
+  double* rec64 = nullptr;  // split: per-point eigen-records of U (Q1 levels), FP64 and FP32
+  float* rec32 = nullptr;
   uint8_t *base = nullptr, *mask = nullptr;
   void *vb = nullptr, *vx = nullptr, *vr = nullptr, *vt = nullptr, *vd = nullptr;
   double eig[4] = {1, 1, 1, 1};
@@ -370,6 +385,11 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     b.vr = cv.take<double>(nd);
     b.vt = cv.take<double>(nd);
     b.vd = cv.take<double>(nd);
+    if (o.stress_split == PF_SPLIT_MIEHE && b.g.p == 1) {
+      const size_t nr = (size_t)split_record_values(b.g.d) * (size_t)b.g.n_cells;
+      b.rec64 = cv.take<double>(nr);
+      b.rec32 = cv.take<float>(nr);
+    }
   }
   const Geom& gf = lev[L - 1].g;
   const size_t nn = gf.n_nodes, nd = gf.n_dofs;
@@ -432,6 +452,7 @@ CellParams level_params(pf_ctx* c, int l, int prec, int mode) {
     const int pi = prec == PF_F64 ? 0 : 1, mi = mode == MODE_APPLY ? 0 : 1;
     cp.variant = b.variant[pi][mi];
     cp.zc = b.zc[pi][mi];
+    if (cp.split) cp.qpd = prec == PF_F64 ? (const void*)b.rec64 : (const void*)b.rec32;
   }
   return cp;
 }
@@ -729,9 +750,10 @@ pf_status ensure_aux(pf_ctx* c) {
   return PF_OK;
 }
 
-// per-level set-up task: diagonal of B~, FP32 copies, eigenvalue CG
+// per-level set-up task: split eigen-records, diagonal of B~, FP32 copies, eigenvalue CG
 pf_status level_task(pf_ctx* c, int l, hipStream_t s) {
   LevelBuf& b = c->lev[l];
+  if (b.rec64) PFF_TRY(launch_split_data(b.g, cparams(c, l), b.U, b.rec64, b.rec32, s));
   PFF_TRY(apply_op<double>(b.g, cparams(c, l), MODE_DIAG, nullptr, b.U, b.phit, b.mask, b.diag, s));
   PFF_TRY(vec_cast<double, float>(b.U32, b.U, b.g.n_dofs, s));
   PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
@@ -1458,7 +1480,9 @@ static const int kNCand = 12;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];
-  if (b.g.p != 1 || c->mat.split) return PF_OK;  // the split runs the generic cell loop
+  if (b.g.p != 1) return PF_OK;
+  // the split has two shapes of its own (one work item per cell, or two wavefronts per cell)
+  const bool split = c->mat.split != PF_SPLIT_NONE;
   hipEvent_t e0, e1;
   PFF_HIP(hipEventCreate(&e0));
   PFF_HIP(hipEventCreate(&e1));
@@ -1474,7 +1498,8 @@ static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
       double best = 1e300;
       int bv = -1, bz = -1;
       for (int k = 0; k < kNCand && st == PF_OK; ++k) {
-        if ((kCand[k][0] == 1 || kCand[k][0] == 3) && b.g.d != 3) {
+        if (((kCand[k][0] == 1 || kCand[k][0] == 3) && b.g.d != 3) ||
+            (split && !(kCand[k][0] == 2 || kCand[k][0] == 4))) {
           b.tune_us[pi][mi][k] = -1.0;
           continue;
         }

@@ -57,6 +57,30 @@ def test_split_apply_all_levels(name):
     assert rel_err(G0 @ x, ref) > 1e-4
 
 
+@pytest.mark.parametrize("name", ["small2d_miehe", "small3d_miehe", "small_lshape_miehe"])
+def test_split_apply_every_shape(name):
+    """Both Q1 shapes of the split apply from the stored eigen-records (one work item per cell,
+    variant 2; displacement and phase-field rows in two wavefronts, variant 4), both operators,
+    both precisions, every level."""
+    from paper_1902_08112_amd import pff
+    s, U, phit, act, H, S = setup_case(name, seed=29)
+    torch = __import__("torch")
+    for l in range(s["n_levels"]):
+        x = np.random.default_rng(300 + l).uniform(-1, 1, H.levels[l].n_dofs)
+        refG, refB = H.mg[l].G @ x, H.mg[l].B @ x
+        for v in (2, 4):
+            for mode in (0, 1):
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F64, mode, v, -1)
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F32, mode, v, -1)
+            y = host(S.jacobian_apply(l, dev(x)))
+            yb = host(S.block_apply(l, dev(x)))
+            y32 = host(S.jacobian_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+            yb32 = host(S.block_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+            e, eb, e32, eb32 = rel_err(y, refG), rel_err(yb, refB), rel_err(y32, refG), rel_err(yb32, refB)
+            print(f"  level {l} shape {v}: {e:.1e} {eb:.1e} FP32 {e32:.1e} {eb32:.1e}", flush=True)
+            assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6 and eb32 <= 2e-6
+
+
 @pytest.mark.parametrize("name", ["tiny2d_miehe", "tiny3d_q2_miehe", "small3d_miehe", "small_lshape_miehe"])
 def test_split_residual_and_diagonal(name):
     s, U, phit, act, H, S = setup_case(name, seed=11)
