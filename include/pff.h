@@ -5,17 +5,22 @@
  * Newton) method for the quasi-monolithic pressurized phase-field fracture
  * problem of Jodlbauer, Langer and Wick, "Matrix-free multigrid solvers for
  * phase-field fracture problems" (arXiv:1902.08112):
- *   - the semi-linear form A(u, phi) (Sec. 2.3, eq. semilinear, no stress
- *     split, time-lagged extrapolation phi~ in the displacement equation) and
- *     its Jacobian G = A'(U) on Q1/Q2 quadrilaterals / hexahedra (Sec. 2.4);
+ *   - the semi-linear form A(u, phi) (Sec. 2.3, eq. semilinear, without a
+ *     stress split or with the Miehe spectral split of Sec. 2.1, time-lagged
+ *     extrapolation phi~ in the displacement equation) and its Jacobian
+ *     G = A'(U) on Q1/Q2 quadrilaterals / hexahedra (Sec. 2.4);
  *   - the matrix-free cell-loop apply y = G~ x (Sec. 4.1) with rows and
  *     columns of the constrained DoFs eliminated (Algorithm 1, step 4);
  *   - coarse-level operators rediscretized at the injected linearization
  *     point G_l(U_l) with the injected active set (Sec. 4.2);
  *   - the monolithic geometric-multigrid V-cycle P_full = MG(G~) with a
  *     block-diagonal Chebyshev-Jacobi smoother and a Chebyshev coarse solve
- *     (Sec. 3.2, Sec. 3.3);
- *   - right-preconditioned FGMRES (Sec. 3, Sec. 5) inside one Newton step.
+ *     (Sec. 3.2, Sec. 3.3), and the block-diagonal alternative
+ *     P_diag = diag(MG(U~), MG(P~)) of Sec. 3.3;
+ *   - right-preconditioned FGMRES (Sec. 3, Sec. 5) inside one Newton step,
+ *     the active-set loop to convergence and the steps of the time loop
+ *     around it (extrapolation of phi~, the pressure of the loading);
+ *   - the energies and boundary loads of Sec. 5 as reductions.
  *
  * Conventions shared by every call
  *   Vector layout: component-major blocks [u_1 | ... | u_d | phi]; each block
@@ -270,10 +275,11 @@ pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi
 /* Quantities of interest of Sec. 5 for the state d_U = (u, phi) on the
  * finest level, as reductions over its cells (deterministic order):
  *   out[0] = crack energy  int G_c/2 ((1 - phi)^2 / eps + eps |grad phi|^2)
- *   out[1] = bulk energy   int g_kappa(phi) E_s(e(u)) + phi^2 p div u  (no split)
+ *   out[1] = bulk energy   int g_kappa(phi) E_s^+(e(u)) + E_s^-(e(u)) + phi^2 p div u
+ * (E_s^+ = E_s, E_s^- = 0 without a split; the Miehe parts with stress_split = PF_SPLIT_MIEHE)
  * at the cell Gauss points.  out is host memory.  Synchronizes. */
 pf_status pf_energies(pf_ctx* ctx, const double* d_U, double out[2], void* stream);
-/* Load on one face of the box: out[0..dim) = int_face g_kappa(phi) sigma(u) n ds
+/* Load on one face of the box: out[0..dim) = int_face (g_kappa(phi) sigma^+(u) + sigma^-(u)) n ds
  * (n the outward normal; the loading curve of Sec. 5 takes one component).
  * face = 2k for {x_k = 0}, 2k+1 for {x_k = extent_k}; only facets of active
  * cells count (the L-shape's hole is not part of the face).  p+1 Gauss points
