@@ -296,13 +296,16 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
 /* Autotuner of the Q1 cell loop (the tensor-product apply of Sec. 4.1).  For
  * every level, precision and operator (mode 0: G~, mode 1: smoother block
  * B~) it times `reps` applies of each candidate kernel shape with HIP events
- * on `stream` and keeps the fastest in the context.  Candidates: variant 2 =
+ * on `stream` and keeps in the context the first candidate (in the order
+ * below) within 3% of the fastest, so that timing noise between near-equal
+ * shapes does not flip the choice.  Candidates: variant 2 =
  * one thread per cell with atomic scatter; variant 4 = two threads per cell
  * (displacement / phase-field rows) with atomic scatter; variant 3 (3D) =
  * 256-thread bricks of cells staged through LDS with atomic scatter;
  * variant 0 / 1 = one wavefront per 8x8 / 16x4 tile of cells marching
  * through chunks of zc node planes with register carries (owner-computes,
- * deterministic).  Requires
+ * deterministic).  With stress_split = PF_SPLIT_MIEHE only variants 2 and 4
+ * exist (the split's record-streaming loops).  Requires
  * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
  * Q2 levels have one kernel and are skipped. */
 pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
@@ -334,6 +337,22 @@ pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len);
  * are the default.  Callers that run many V-cycles per linearization (or that
  * need the launch sequence fixed) enable it. */
 pf_status pf_set_graphs(pf_ctx* ctx, int enable);
+
+/* How the coarsest level's Chebyshev solve (Sec. 3.2.2) runs.  The solve is a fixed
+ * polynomial in the level operator, so every mode computes the same linear map:
+ *   PF_COARSE_AUTO  (default) for a Q1 coarsest level of at most 1024 DoFs without the
+ *                   split, its dense matrix is formed at pf_set_linearization (one
+ *                   workgroup per unit vector) and every V-cycle applies it as one
+ *                   matvec; otherwise as PF_COARSE_FUSED;
+ *   PF_COARSE_FUSED all sweeps in one single-workgroup launch (Q1 levels up to 4096 DoFs),
+ *                   else as PF_COARSE_STEPS;
+ *   PF_COARSE_STEPS one launch per operator apply and Chebyshev step.
+ * After a change to AUTO, or after pf_set_pressure or new level-0 eigenvalue bounds, the
+ * fused kernel serves until the next pf_set_linearization rebuilds the matrix. */
+#define PF_COARSE_AUTO 0
+#define PF_COARSE_FUSED 1
+#define PF_COARSE_STEPS 2
+pf_status pf_set_coarse_mode(pf_ctx* ctx, int mode);
 
 /* Change the V-cycle precision used by pf_newton_step (PF_F64 or PF_F32). */
 pf_status pf_set_vcycle_precision(pf_ctx* ctx, int prec);

@@ -46,8 +46,10 @@ __device__ void wg_apply(const CellParams& cp, const double* x, double* y, const
   __syncthreads();
 }
 
-// COUPLE: the sweep residuals b - A x use the full G~ (P_full) or the block-diagonal B~ (P_diag)
-template <int D, bool COUPLE>
+// COUPLE: the sweep residuals b - A x use the full G~ (P_full) or the block-diagonal B~ (P_diag).
+// COLUMNS: workgroup j solves for b = e_j (0 if DoF j is constrained) and writes x to column j of
+// the dense coarse-solve matrix x = S b (column-major, x + j n; r + j n is its scratch).
+template <int D, bool COUPLE, bool COLUMNS>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, CoarseCoef cc, const double* U,
                                                                  const double* phit, const uint8_t* mask,
                                                                  const double* diag, const double* b, double* x,
@@ -56,15 +58,24 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
   const int64_t nn = cp.n_nodes, n = (int64_t)(D + 1) * nn, nu = (int64_t)D * nn;
   double* vd = lds;      // apply operand: the Chebyshev direction, or x at a sweep start
   double* vt = lds + n;  // apply result
+  int64_t col = -1;
+  if (COLUMNS) {
+    col = blockIdx.x;
+    x += col * n;
+    r += col * n;
+    const int cc_ = (int)(col / nn);
+    if (mask[col - (int64_t)cc_ * nn] & mask_bit(cc_, D)) col = -1;  // constrained: the zero column
+  }
+  auto bval = [&](int64_t i) -> double { return COLUMNS ? (i == col ? 1.0 : 0.0) : b[i]; };
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
   for (int sw = 0; sw < cc.sweeps; ++sw) {
     if (sw == 0) {
-      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = b[i];
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = bval(i);
     } else {
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) vd[i] = x[i];
       __syncthreads();
       wg_apply<D, COUPLE>(cp, vd, vt, U, phit, mask);
-      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = b[i] - vt[i];
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = bval(i) - vt[i];
     }
     for (int k = 0; k < cc.degree; ++k) {
       if (k > 0) wg_apply<D, false>(cp, vd, vt, U, phit, mask);
@@ -88,11 +99,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
 }
 
 // Q1 levels up to kCoarseMaxDofs and degrees up to kCoarseMaxDegree; *handled = false otherwise.
-// couple: sweep residuals with G~ (P_full) or with B~ (P_diag)
+// couple: sweep residuals with G~ (P_full) or with B~ (P_diag).  columns: build the dense matrix of
+// the solve instead (n workgroups; x and r hold n x n doubles each, b unused).
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, bool couple, hipStream_t s, bool* handled) {
+                              double* x, double* r, bool couple, hipStream_t s, bool* handled, bool columns) {
   *handled = false;
   if (g.p != 1 || degree > kCoarseMaxDegree || degree < 1 || g.n_dofs > kCoarseMaxDofs) return PF_OK;
   CoarseCoef cc;
@@ -105,16 +117,68 @@ pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, i
     cc.c2[1][k] = c2p[k];
   }
   const size_t lds = 2 * (size_t)g.n_dofs * sizeof(double);
-  if (g.d == 2 && couple)
-    k_coarse_solve<2, true><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
-  else if (g.d == 2)
-    k_coarse_solve<2, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
-  else if (couple)
-    k_coarse_solve<3, true><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
-  else
-    k_coarse_solve<3, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  const unsigned nwg = columns ? (unsigned)g.n_dofs : 1u;
+  if (columns) {
+    // many concurrent columns: two wavefronts per column keep the chip full in one round (the
+    // single solve uses kCoarseThreads to finish one column fast)
+    const int bt = 128;
+    if (g.d == 2 && couple)
+      k_coarse_solve<2, true, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else if (g.d == 2)
+      k_coarse_solve<2, false, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else if (couple)
+      k_coarse_solve<3, true, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else
+      k_coarse_solve<3, false, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  } else {
+    if (g.d == 2 && couple)
+      k_coarse_solve<2, true, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else if (g.d == 2)
+      k_coarse_solve<2, false, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else if (couple)
+      k_coarse_solve<3, true, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+    else
+      k_coarse_solve<3, false, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+  }
   PFF_CHECK_LAUNCH();
   *handled = true;
+  return PF_OK;
+}
+
+// T = transpose of the column-major n x n matrix C (T row-major = C column-major read by rows)
+__global__ __launch_bounds__(256) void k_coarse_transpose(const double* __restrict__ C, double* __restrict__ T,
+                                                          int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n * n) return;
+  const int64_t i = k / n, j = k - i * n;  // T[i][j] = C[j * n + i]
+  T[k] = C[j * n + i];
+}
+
+pf_status coarse_transpose(const double* C, double* T, int64_t n, hipStream_t s) {
+  if (n <= 0) return PF_OK;
+  k_coarse_transpose<<<(unsigned)((n * n + 255) / 256), 256, 0, s>>>(C, T, n);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+// x = S b with the row-major dense coarse-solve matrix S (n x n): one wavefront per row, lanes
+// stride the columns (independent loads), a shuffle reduction ends the row
+__global__ __launch_bounds__(256) void k_coarse_matvec(const double* __restrict__ S, const double* __restrict__ b,
+                                                       double* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double* row = S + i * n;
+  double acc = 0.0;
+  for (int64_t j = lane; j < n; j += 64) acc += row[j] * b[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) x[i] = acc;
+}
+
+pf_status coarse_matvec(const double* S, const double* b, double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return PF_OK;
+  k_coarse_matvec<<<(unsigned)((n + 3) / 4), 256, 0, s>>>(S, b, x, n);
+  PFF_CHECK_LAUNCH();
   return PF_OK;
 }
 

@@ -38,7 +38,10 @@ pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face,
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
                               const double* c2u, const double* c1p, const double* c2p, const double* U,
                               const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, bool couple, hipStream_t s, bool* handled);
+                              double* x, double* r, bool couple, hipStream_t s, bool* handled,
+                              bool columns = false);
+pf_status coarse_matvec(const double* S, const double* b, double* x, int64_t n, hipStream_t s);
+pf_status coarse_transpose(const double* C, double* T, int64_t n, hipStream_t s);
 
 template <>
 pf_status launch_cell<double>(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
@@ -204,7 +207,13 @@ struct pf_ctx {
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
   bool use_graphs = false;  // eager launches: a capture per linearization costs more than replays save
-  bool fused_coarse = true;  // coarse Chebyshev solve in one single-workgroup launch
+  // coarse solve: PF_COARSE_AUTO = the dense matrix of the fixed Chebyshev solve (small Q1 coarse
+  // levels, built once per linearization) else the single-workgroup kernel; PF_COARSE_FUSED;
+  // PF_COARSE_STEPS = one launch per operator apply and vector step
+  int coarse_mode = PF_COARSE_AUTO;
+  double* Sc = nullptr;  // dense coarse-solve matrix: built column-major here (Rc: per-column scratch),
+  double* Rc = nullptr;  // then transposed into Rc, which the V-cycle reads row by row
+  bool coarse_dense_ok = false;
   void drop_graphs() {
     for (int k = 0; k < 2; ++k) {
       if (vexec[k]) hipGraphExecDestroy(vexec[k]);
@@ -363,6 +372,16 @@ Geom level_geom(const pf_mesh& m, int l) {
   return g;
 }
 
+// The coarse solve is a fixed linear map during a Newton step (a Chebyshev polynomial with
+// coefficients fixed by the level's lambda bounds).  For a small Q1 coarsest level it is
+// cheaper to form its matrix once per linearization, one workgroup per unit vector, and apply
+// it as one dense matvec per V-cycle than to run 2 x 20 latency-bound steps every time.
+constexpr int64_t kDenseCoarseMaxDofs = 1024;
+bool dense_coarse_eligible(const Geom& g0, const pf_options& o) {
+  return g0.p == 1 && g0.n_dofs <= kDenseCoarseMaxDofs && o.stress_split == PF_SPLIT_NONE &&
+         o.coarse_degree <= 64;
+}
+
 // Carve every device buffer; with base == nullptr only the size is computed.
 size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   Carver cv{base};
@@ -413,6 +432,12 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* qpart = cv.take<double>(3 * 1024 + 64);
   double* vin = cv.take<double>(nd);
   double* vout = cv.take<double>(nd);
+  double *Sc = nullptr, *Rc = nullptr;
+  if (dense_coarse_eligible(lev[0].g, o)) {
+    const size_t n0 = (size_t)lev[0].g.n_dofs;
+    Sc = cv.take<double>(n0 * n0);
+    Rc = cv.take<double>(n0 * n0);
+  }
   if (c) {
     c->lev = lev;
     c->M = M;
@@ -434,6 +459,8 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->qpart = qpart;
     c->vin = vin;
     c->vout = vout;
+    c->Sc = Sc;
+    c->Rc = Rc;
   }
   return cv.off + 256;
 }
@@ -564,7 +591,8 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
   const pf_options& o = c->opt;
   const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
   const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
-  if (c->fused_coarse && !c->mat.split) {
+  if (c->coarse_mode == PF_COARSE_AUTO && c->coarse_dense_ok) return coarse_matvec(c->Rc, bb, x, b.g.n_dofs, s);
+  if (c->coarse_mode != PF_COARSE_STEPS && !c->mat.split) {
     const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
     bool handled = false;
     PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
@@ -577,6 +605,24 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
     // sweep 0 starts from x = 0 (r = b), later sweeps from r = b - G~ x
     PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, sw == 0 ? 1 : 2, bb, false, s));
   }
+  return PF_OK;
+}
+
+// the dense matrix of the coarse solve for the current level-0 data and lambda bounds
+pf_status build_coarse_dense(pf_ctx* c, hipStream_t s) {
+  c->coarse_dense_ok = false;
+  if (!c->Sc || c->coarse_mode != PF_COARSE_AUTO || c->mat.split) return PF_OK;
+  LevelBuf& b = c->lev[0];
+  const pf_options& o = c->opt;
+  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
+  const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
+  const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
+  bool handled = false;
+  PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
+                              cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, nullptr, c->Sc, c->Rc,
+                              cycle_mode(c) == MODE_APPLY, s, &handled, true));
+  if (handled) PFF_TRY(coarse_transpose(c->Sc, c->Rc, b.g.n_dofs, s));
+  c->coarse_dense_ok = handled;
   return PF_OK;
 }
 
@@ -787,6 +833,7 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
   PFF_TRY(level_task(c, L, s));
   for (int l = 0; l < L; ++l) PFF_HIP(hipStreamWaitEvent(s, c->aux_ev[l], 0));
   PFF_TRY(eig_readback(c, s));
+  PFF_TRY(build_coarse_dense(c, s));
   PFF_HIP(hipStreamSynchronize(s));
   c->has_lin = true;
   c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle
@@ -1235,6 +1282,7 @@ pf_status pf_set_eig_bounds(pf_ctx* ctx, int level, const double in[4]) {
   for (int k = 0; k < 4; ++k) b.eig[k] = in[k];
   b.eig_fixed = true;
   ctx->drop_graphs();
+  if (level == 0) ctx->coarse_dense_ok = false;  // the fused kernel serves until the next set-up
   return PF_OK;
 }
 
@@ -1446,6 +1494,8 @@ pf_status pf_set_pressure(pf_ctx* ctx, double pressure) {
     return PF_ERR_INVALID_ARG;
   }
   ctx->mat.p = pressure;
+  ctx->coarse_dense_ok = false;  // the operator changed: the fused kernel serves until the next set-up
+  ctx->drop_graphs();
   return PF_OK;
 }
 
@@ -1477,6 +1527,7 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
 static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {0, 32}, {0, 64},
                                {1, 4}, {1, 8}, {1, 16}, {1, 32}};
 static const int kNCand = 12;
+static const double kTuneTie = 0.03;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];
@@ -1519,10 +1570,16 @@ static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
         }
         const double us = 1e3 * ms / reps;
         b.tune_us[pi][mi][k] = us;
-        if (us < best) {
-          best = us;
+        best = std::min(best, us);
+      }
+      // the earliest candidate within kTuneTie of the fastest: timing noise between near-equal
+      // shapes does not flip the choice from run to run
+      for (int k = 0; k < kNCand && st == PF_OK; ++k) {
+        const double us = b.tune_us[pi][mi][k];
+        if (us > 0.0 && us <= best * (1.0 + kTuneTie)) {
           bv = kCand[k][0];
           bz = kCand[k][1];
+          break;
         }
       }
       b.variant[pi][mi] = bv;
@@ -1617,6 +1674,18 @@ pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len) {
     return PF_ERR_INVALID_ARG;
   }
   std::memcpy(buf, o.c_str(), o.size() + 1);
+  return PF_OK;
+}
+
+pf_status pf_set_coarse_mode(pf_ctx* ctx, int mode) {
+  NEED_CTX();
+  if (mode != PF_COARSE_AUTO && mode != PF_COARSE_FUSED && mode != PF_COARSE_STEPS) {
+    set_error("mode must be PF_COARSE_AUTO, PF_COARSE_FUSED or PF_COARSE_STEPS");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (mode != ctx->coarse_mode) ctx->coarse_dense_ok = false;  // AUTO builds its matrix at the next set-up
+  ctx->coarse_mode = mode;
+  ctx->drop_graphs();
   return PF_OK;
 }
 

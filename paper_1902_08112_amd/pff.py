@@ -21,6 +21,7 @@ PF_ERR_WORKSPACE, PF_ERR_NOT_CONVERGED, PF_ERR_NONFINITE = 4, 5, 6
 PF_F64, PF_F32 = 0, 1
 PF_PREC_FULL, PF_PREC_DIAG = 0, 1
 PF_SPLIT_NONE, PF_SPLIT_MIEHE = 0, 1
+PF_COARSE_AUTO, PF_COARSE_FUSED, PF_COARSE_STEPS = 0, 1, 2
 PF_BOX, PF_LSHAPE = 0, 1
 PF_MASK_PHI = 8
 
@@ -93,6 +94,7 @@ SIGNATURES = {
     "pf_set_vcycle_precision": (I, [VP, I]),
     "pf_autotune": (I, [VP, I, VP]),
     "pf_set_graphs": (I, [VP, I]),
+    "pf_set_coarse_mode": (I, [VP, I]),
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
@@ -489,6 +491,10 @@ class Solver:
 
     def set_graphs(self, enable):
         _check(lib().pf_set_graphs(self.ctx, 1 if enable else 0), "pf_set_graphs")
+
+    def set_coarse_mode(self, mode):
+        """PF_COARSE_AUTO (dense matrix of the coarse solve when small), PF_COARSE_FUSED or PF_COARSE_STEPS."""
+        _check(lib().pf_set_coarse_mode(self.ctx, mode), "pf_set_coarse_mode")
 
     def set_kernel_timing(self, enable):
         """Bracket every finest-level FP64 Jacobian cell kernel with HIP events (see pff.h)."""
