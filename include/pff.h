@@ -118,7 +118,7 @@ typedef struct pf_options {
                               Sec. 5 use rtol 1e-4 with a small floor) */
   int preconditioner;      /* PF_PREC_FULL (default, the paper's choice) or PF_PREC_DIAG */
   int stress_split;        /* PF_SPLIT_NONE (default) or PF_SPLIT_MIEHE: the model's energy split
-                              (pf_setup only; the batched solver supports PF_SPLIT_NONE) */
+                              (the batched solver evaluates the split on the fly in every mode) */
 } pf_options;
 
 typedef struct pf_newton_report {

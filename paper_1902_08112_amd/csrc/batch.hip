@@ -39,6 +39,7 @@ struct BView {
   const int64_t* node_off;  // B+1
   const int64_t* cell_off;  // B+1
   int B, d, p;
+  int split;  // PF_SPLIT_MIEHE: every mode evaluates the split on the fly (generic cell math, FP64)
   int64_t n_dofs, n_nodes, n_cells;
 };
 
@@ -64,7 +65,7 @@ static inline int64_t bgrid(int64_t n, int bs = 256) {
 }
 
 // ---------------------------------------------------------------------------- cell loop
-template <int D, int P, typename T, int MODE>
+template <int D, int P, typename T, int MODE, bool SPLIT>
 __global__ __launch_bounds__(128) void k_b_cell(BView v, const T* __restrict__ x, const T* __restrict__ U,
                                                 const T* __restrict__ phit, const uint8_t* __restrict__ mask,
                                                 T* __restrict__ y) {
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(128) void k_b_cell(BView v, const T* __restrict__ x
     const T* po = phit + node;
     const uint8_t* mo = mask + node;
     T* yo = y + dof;
-    if constexpr (P == 1 && (MODE == MODE_APPLY || MODE == MODE_BLOCK)) {
+    if constexpr (!SPLIT && P == 1 && (MODE == MODE_APPLY || MODE == MODE_BLOCK)) {
       const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
       q1_cell_atomic<D, T, MODE == MODE_APPLY>(cp, g0, xo, Uo, po, mo, yo);
     } else {
@@ -101,51 +102,53 @@ __global__ __launch_bounds__(128) void k_b_cell(BView v, const T* __restrict__ x
         for (int k = 0; k < D; ++k) w += (int64_t)(P * c3[k] + TT::idx(a, k)) * cp.ns[k];
         g[a] = w;
       }
-      T xv[D + 1][NL], uv[D + 1][NL], pv[NL];
+      // the split is evaluated in FP64 whatever the storage type
+      using TC = typename std::conditional<SPLIT, double, T>::type;
+      TC xv[D + 1][NL], uv[D + 1][NL], pv[NL];
       uint8_t mk[NL];
 #pragma unroll
       for (int a = 0; a < NL; ++a) {
         mk[a] = kMasked ? mo[g[a]] : 0;
-        pv[a] = po[g[a]];
+        pv[a] = (TC)po[g[a]];
 #pragma unroll
         for (int i = 0; i <= D; ++i) {
-          uv[i][a] = Uo[i * nn + g[a]];
-          const T val = kDir ? xo[i * nn + g[a]] : T(0);
-          xv[i][a] = (kMasked && (mk[a] & mask_bit(i, D))) ? T(0) : val;
+          uv[i][a] = (TC)Uo[i * nn + g[a]];
+          const TC val = kDir ? (TC)xo[i * nn + g[a]] : TC(0);
+          xv[i][a] = (kMasked && (mk[a] & mask_bit(i, D))) ? TC(0) : val;
         }
       }
-      T out[D + 1][NL];
-      generic_cell<D, P, T, MODE>(cp, xv, uv, pv, out);
+      TC out[D + 1][NL];
+      generic_cell<D, P, TC, MODE, SPLIT>(cp, xv, uv, pv, out);
 #pragma unroll
       for (int a = 0; a < NL; ++a)
 #pragma unroll
         for (int i = 0; i <= D; ++i) {
           if (kMasked && (mk[a] & mask_bit(i, D))) continue;
-          atomicAdd(&yo[i * nn + g[a]], out[i][a]);
+          atomicAdd(&yo[i * nn + g[a]], (T)out[i][a]);
         }
     }
   }
 }
 
-template <int D, int P, typename T>
-static pf_status b_cell_dp(const BView& v, int mode, const T* x, const T* U, const T* phit, const uint8_t* mask,
-                           T* y, hipStream_t s) {
+template <int D, int P, typename T, bool SPLIT>
+static pf_status b_cell_dps(const BView& v, int mode, const T* x, const T* U, const T* phit, const uint8_t* mask,
+                            T* y, hipStream_t s) {
   const int64_t nb = bgrid(v.n_cells, 128);
   switch (mode) {
     case MODE_APPLY:
-      k_b_cell<D, P, T, MODE_APPLY><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
+      k_b_cell<D, P, T, MODE_APPLY, SPLIT><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
       break;
     case MODE_BLOCK:
-      k_b_cell<D, P, T, MODE_BLOCK><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
+      k_b_cell<D, P, T, MODE_BLOCK, SPLIT><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
       break;
     default:
       if constexpr (std::is_same<T, double>::value) {
         if (mode == MODE_RAW)
-          k_b_cell<D, P, T, MODE_RAW><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
+          k_b_cell<D, P, T, MODE_RAW, SPLIT><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
         else if (mode == MODE_RESID)
-          k_b_cell<D, P, T, MODE_RESID><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
+          k_b_cell<D, P, T, MODE_RESID, SPLIT><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
         else
-          k_b_cell<D, P, T, MODE_DIAG><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
+          k_b_cell<D, P, T, MODE_DIAG, SPLIT><<<nb, 128, 0, s>>>(v, x, U, phit, mask, y);
       } else {
         set_error("FP32 batched cell loop supports the apply modes only");
         return PF_ERR_UNSUPPORTED;
@@ -153,6 +156,13 @@ static pf_status b_cell_dp(const BView& v, int mode, const T* x, const T* U, con
   }
   PFF_CHECK_LAUNCH();
   return PF_OK;
+}
+
+template <int D, int P, typename T>
+static pf_status b_cell_dp(const BView& v, int mode, const T* x, const T* U, const T* phit, const uint8_t* mask,
+                           T* y, hipStream_t s) {
+  return v.split ? b_cell_dps<D, P, T, true>(v, mode, x, U, phit, mask, y, s)
+                 : b_cell_dps<D, P, T, false>(v, mode, x, U, phit, mask, y, s);
 }
 
 template <typename T>
@@ -425,6 +435,7 @@ struct BLevel {
   double* d_coef_c = nullptr;  // [coarse_degree][B][4] (level 0)
   std::vector<double> eig;     // [B][4]
   int d = 0, p = 0, B = 0;
+  int split = PF_SPLIT_NONE;
   BView view() const {
     BView v;
     v.inst = d_inst;
@@ -434,6 +445,7 @@ struct BLevel {
     v.B = B;
     v.d = d;
     v.p = p;
+    v.split = split;
     v.n_dofs = n_dofs;
     v.n_nodes = n_nodes;
     v.n_cells = n_cells;
@@ -558,6 +570,7 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
     bl.B = n;
     bl.d = d;
     bl.p = meshes[0].degree;
+    bl.split = o.stress_split;
     bl.h_dof.assign(n + 1, 0);
     bl.h_node.assign(n + 1, 0);
     bl.h_cell.assign(n + 1, 0);
@@ -1164,10 +1177,6 @@ pf_status pf_batch_workspace_size(const pf_mesh* meshes, int n, const pf_options
   pf_default_options(&o);
   if (opt) o = *opt;
   PFF_TRY(validate_batch(meshes, nullptr, n, &o));
-  if (o.stress_split != PF_SPLIT_NONE) {
-    set_error("the batched solver supports stress_split = PF_SPLIT_NONE only");
-    return PF_ERR_UNSUPPORTED;
-  }
   for (int b = 0; b < n; ++b) {
     size_t tmp = 0;
     PFF_TRY(pf_workspace_size(&meshes[b], &o, &tmp));
@@ -1187,10 +1196,6 @@ pf_status pf_batch_setup(const pf_mesh* meshes, const double* materials, int n, 
   pf_default_options(&o);
   if (opt) o = *opt;
   PFF_TRY(validate_batch(meshes, materials, n, &o));
-  if (o.stress_split != PF_SPLIT_NONE) {
-    set_error("the batched solver supports stress_split = PF_SPLIT_NONE only");
-    return PF_ERR_UNSUPPORTED;
-  }
   for (int b = 0; b < n; ++b) {
     size_t tmp = 0;
     PFF_TRY(pf_workspace_size(&meshes[b], &o, &tmp));
@@ -1221,7 +1226,7 @@ pf_status pf_batch_setup(const pf_mesh* meshes, const double* materials, int n, 
     mm.eps = m[3];
     mm.kappa = m[4];
     mm.p = m[5];
-    mm.split = PF_SPLIT_NONE;
+    mm.split = o.stress_split;
     c->mats.push_back(mm);
   }
   bcarve(c, meshes, n, o, reinterpret_cast<char*>(d_workspace), &c->mats);

@@ -571,7 +571,12 @@ class BatchSolver:
             m = s["material"]
             mats += [m["E"], m["nu"], m["G_c"], m["eps"], m["kappa"], m["pressure"]]
         self.mats = (D * (6 * n))(*mats)
-        self.opt = opt or pf_default_options()
+        self.opt = Options.from_buffer_copy(opt) if opt is not None else pf_default_options()
+        splits = {s["material"].get("split", "none") for s in self.specs}
+        if len(splits) > 1:
+            raise ValueError("the instances of a batch share one energy split")
+        if "split" in self.specs[0]["material"]:
+            self.opt.stress_split = {"none": PF_SPLIT_NONE, "miehe": PF_SPLIT_MIEHE}[splits.pop()]
         nb = C.c_size_t(0)
         _check(lib().pf_batch_workspace_size(self.meshes, n, C.byref(self.opt), C.byref(nb)),
                "pf_batch_workspace_size")

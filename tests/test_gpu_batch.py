@@ -173,3 +173,46 @@ def test_batched_family_64_instances():
         assert abs(nb - ns) <= band
         if nb == ns:
             assert e <= 1e-6
+
+
+def test_batch_split_matches_oracle_and_single_instances():
+    """The Miehe split in the batched solver (evaluated on the fly): applies on every level against
+    the oracle's split operators, and Newton steps against single-instance split steps."""
+    specs = [dict(s, material=dict(s["material"], split="miehe")) for s in small_batch(2, seed=5)[:3]]
+    print(f"[case] batch split n={len(specs)}", flush=True)
+    BS = batch_solver(specs, eig_cg_steps=2)
+    assert BS.opt.stress_split == 1
+    Us, pts, acts, Hs = [], [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 110 + b)
+        act = W.random_active(s, 120 + b, 0.1)
+        H = oracle_hierarchy(s)
+        H.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+        Us.append(U), pts.append(phit), acts.append(act), Hs.append(H)
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    torch = __import__("torch")
+    for l in range(BS.L):
+        xs = [np.random.default_rng(130 + b + 7 * l).uniform(-1, 1, Hs[b].levels[l].n_dofs) for b in range(len(specs))]
+        ys = BS.unpack(BS.jacobian_apply(l, BS.pack(xs, level=l)), level=l)
+        ys32 = BS.unpack(BS.jacobian_apply(l, BS.pack(xs, level=l).to(torch.float32)), level=l)
+        for b in range(len(specs)):
+            ref = Hs[b].mg[l].G @ xs[b]
+            e, e32 = rel_err(ys[b], ref), rel_err(ys32[b].astype(np.float64), ref)
+            print(f"  level {l} inst {b}: rel {e:.1e} FP32 {e32:.1e}", flush=True)
+            assert e <= 1e-12 and e32 <= 2e-6
+    states = [W.make_state(s) for s in specs]
+    BS2 = batch_solver(specs)
+    U = BS2.pack([st[0] for st in states])
+    _, reps = BS2.newton_step(U, BS2.pack([st[1] for st in states]), BS2.pack([st[2] for st in states], nodes=True))
+    Ub = BS2.unpack(U)
+    for b, s in enumerate(specs):
+        U0, Uold, phit = states[b]
+        S = gpu_solver(s)
+        Ud = dev(U0)
+        _, rep = S.newton_step(Ud, dev(Uold), dev(phit))
+        e = rel_err(Ub[b] - U0, host(Ud) - U0)
+        print(f"  newton inst {b}: batch its {reps[b]['gmres_iters']} |A| {reps[b]['n_active']}; single its "
+              f"{rep.gmres_iters} |A| {rep.n_active}; rel diff {e:.1e}", flush=True)
+        assert reps[b]["converged"] and reps[b]["rel_residual"] <= 1e-8
+        assert reps[b]["n_active"] == rep.n_active and abs(reps[b]["gmres_iters"] - rep.gmres_iters) <= 1
+        assert e <= 1e-6
