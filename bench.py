@@ -7,20 +7,26 @@ library (residual, active set, level data, diagonals, eigenvalue estimates,
 FGMRES with the V-cycle to a 1e-8 true relative residual, update), starting
 each time from the same iterate U_k (the reset copy is inside the timed loop).
 
-value = fine-level DoFs per second of Newton steps with the plain FP64 V-cycle
-(the workload's own setting); the FP32-V-cycle step time and the speedup are
-reported beside it.  The roofline entry is the FP64 Jacobian cell kernel on
-the finest level (dominant kernel): the library brackets each of its launches
-inside the timed FP64 Newton steps with HIP events on the launch stream
-(pf_set_kernel_timing), and achieved = algorithmic flops per launch / mean
-launch duration.  traffic = HBM bytes per launch from the committed rocprofv3
-FETCH_SIZE / WRITE_SIZE summary of this command (profiles/), while the
-kernel's sources are unchanged.  After the timed region a plain device copy of
-one fine-level vector runs (the counters' calibration).  cpu_baseline: the
-FP64 oracle's Newton step on a 32^3 sample of the same workload (same crack,
-material and eps), one core.
+value = fine-level DoFs per second of Newton steps in the workload's own
+V-cycle precision; the other precision's step time and the speedup are
+reported beside it.  Inside the timed FP64 Newton steps the library brackets
+every 4th launch of the two finest-level FP64 cell kernels, the Jacobian G~
+and the smoother's block operator B~, with HIP events on the launch stream
+(pf_set_kernel_timing); "kernels" reports both (launches per step, mean launch
+duration, achieved = algorithmic flops or bytes per launch / mean duration),
+and the roofline entry is the one with the larger time per step among those
+with an algorithmic count (B~ is counted on unsplit Q1 levels, where it reads
+stored per-point coefficients).  traffic = HBM bytes per launch from the
+committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of this command
+(profiles/<workload>_apply_traffic.json for G~, _block_traffic.json for B~),
+while the kernel's sources are unchanged.  After the timed region a plain
+device copy of one fine-level vector runs (the counters' calibration).
+With --tuning-cache the autotuner's choices are read from (or written to) a
+file, so that profiled runs use the choices of an unprofiled one.
+cpu_baseline: the FP64 oracle's Newton step on a 32^3 sample of the same
+workload (same crack, material and eps), one core.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--no-cpu] [--tuning-cache F]
 """
 from __future__ import annotations
 
@@ -44,26 +50,38 @@ BYTES_PER_DOF_F64 = {2: 8 * 3 + (8 + 1) / 3.0, 3: 8 * 3 + (8 + 1) / 4.0}
 # record bytes per cell (tr e, eigenvalues, eigenvectors: 8 values x 8 points 3D, 5 x 4 2D, FP64)
 SPLIT_FLOP_PER_CELL = {2: 656.0 + 4 * 76.0, 3: 2496.0 + 8 * 240.0}
 SPLIT_REC_BYTES_PER_CELL = {2: 5 * 4 * 8.0, 3: 8 * 8 * 8.0}
+# block operator B~ (the smoother's operator) on unsplit Q1 levels, which reads its phase-field
+# coefficient c_phi JxW per Gauss point: the same counting rule over the fields B~ touches
+# (forward (d+1)(I+Gr) + I, backward (d+1)(I+Gr), 36 flops per 3D and 21 per 2D point), and
+# x, y at d+1 values, phi~ and the mask per node plus 2^d FP64 coefficients per cell
+BLOCK_FLOP_PER_CELL = {2: 396.0, 3: 1512.0}
+BLOCK_BYTES_PER_NODE_F64 = {2: 8 * 6 + 8 + 1.0, 3: 8 * 8 + 8 + 1.0}
+BLOCK_COEF_BYTES_PER_CELL = {2: 4 * 8.0, 3: 8 * 8.0}
+# every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
+# timed FP64 steps (a bracket delays the stream by a few microseconds)
+KT_EVERY = 4
 
 
-# kernel of the finest-level FP64 Jacobian apply for a tuning variant (as rocprofv3 names it)
-def kernel_name(dim, degree, variant, split=False):
+# kernel of the finest-level FP64 Jacobian (mode 0) or block (mode 1) apply for a tuning variant,
+# as rocprofv3 names it
+def kernel_name(dim, degree, variant, split=False, mode=0):
     if split and degree == 1:
-        return f"k_q1s<{dim}, double, 0, {1 if variant == 2 else 2}>"
+        return f"k_q1s<{dim}, double, {mode}, {1 if variant == 2 else 2}>"
     if degree == 2:
-        return "k_q2_3d<double, 0>" if dim == 3 else "k_cell_generic<2, 2, double, 0>"
+        return f"k_q2_3d<double, {mode}>" if dim == 3 else f"k_cell_generic<2, 2, double, {mode}>"
     if dim == 2:
-        return {0: "k_q1_2d<double, 0>", 2: "k_q1_2d_atomic<double, 0>",
-                4: "k_q1_split<2, double, 0>"}.get(variant, "k_q1_2d<double, 0>")
-    return {0: "k_q1_3d<double, 0, 8, 8>", 1: "k_q1_3d<double, 0, 16, 4>", 2: "k_q1_3d_atomic<double, 0>",
-            3: "k_q1_3d_brick<double, 0>", 4: "k_q1_split<3, double, 0>"}.get(variant, "?")
+        return {0: f"k_q1_2d<double, {mode}>", 2: f"k_q1_2d_atomic<double, {mode}>",
+                4: f"k_q1_split<2, double, {mode}>"}.get(variant, f"k_q1_2d<double, {mode}>")
+    return {0: f"k_q1_3d<double, {mode}, 8, 8>", 1: f"k_q1_3d<double, {mode}, 16, 4>",
+            2: f"k_q1_3d_atomic<double, {mode}>", 3: f"k_q1_3d_brick<double, {mode}>",
+            4: f"k_q1_split<3, double, {mode}>"}.get(variant, "?")
 
 
-def measured_traffic(workload, kname):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None if there is none for this kernel
-    or its sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_apply_traffic.json")
+def measured_traffic(workload, kname, role="apply"):
+    """HBM bytes per launch of a kernel (role "apply": the Jacobian, "block": B~) from the
+    committed rocprofv3 --pmc summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy), or None
+    if there is none for this kernel or its sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{role}_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -85,6 +103,8 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of autotuner choices: read if it holds this mesh, else written")
     ap.add_argument("--cpu-sample", type=int, default=32)
     return ap.parse_args()
 
@@ -266,7 +286,7 @@ def main():
         # the FP64 steps also record the duration of every finest-level FP64 Jacobian cell
         # kernel launch with HIP events on the launch stream (the dominant kernel)
         if prec == pff.PF_F64:
-            S.set_kernel_timing(True)
+            S.set_kernel_timing(pff.PF_KTIME_JACOBIAN | pff.PF_KTIME_BLOCK, every=KT_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = run_steps(k, prec)
@@ -275,21 +295,21 @@ def main():
         kt = None
         if prec == pff.PF_F64:
             S.set_kernel_timing(False)
-            kt = S.kernel_timing()
+            kt = {op: S.kernel_timing(op, launches=True) for op in (pff.PF_KTIME_JACOBIAN, pff.PF_KTIME_BLOCK)}
         return dt, reps, kt
 
     base_prec = pff.PF_F32 if s.get("vcycle") == "f32" else pff.PF_F64
     other_prec = pff.PF_F64 if base_prec == pff.PF_F32 else pff.PF_F32
     # one step sets the linearization point; the autotuner then picks the cell-loop shape per level
     run_steps(1, base_prec)
-    tuning = S.autotune(reps=10) if not a.no_tune else None
+    tuning = S.autotune(reps=10, cache_path=a.tuning_cache) if not a.no_tune else None
     run_steps(a.warmup, base_prec)
     t_base, reps, kt_base = timed(a.steps, base_prec)
     run_steps(a.warmup, other_prec)
     t_other, reps_o, kt_other = timed(a.steps, other_prec)
     t64, t32 = (t_base, t_other) if base_prec == pff.PF_F64 else (t_other, t_base)
     r64, r32 = (reps, reps_o) if base_prec == pff.PF_F64 else (reps_o, reps)
-    kt = kt_base if base_prec == pff.PF_F64 else kt_other   # (count, mean, min, max) in s
+    kt = kt_base if base_prec == pff.PF_F64 else kt_other   # op -> (launches, count, mean, min, max) in s
 
     # dominant kernel: FP64 Jacobian apply on the finest level (linearization of the last step)
     x = torch.from_numpy(np.random.default_rng(0).uniform(-1, 1, n_vec)).cuda()
@@ -318,33 +338,60 @@ def main():
 
     info = S.levels[L]
     n_cells = int(info.n_active_cells)
+    n_nodes = int(info.n_domain_nodes)
     split = s["material"].get("split", "none") == "miehe" and s["degree"] == 1
+    steps_fp64 = a.steps
+
+    def kernel_entry(op, flops, bytes_, bound, kname, role, t_fallback=None):
+        launches, k_count, k_mean, k_min, k_max = kt[op]
+        t_kernel = k_mean if k_count > 0 else t_fallback
+        e = {"kernel": kname, "launches_per_step": launches / steps_fp64, "launches_timed": k_count,
+             "timed_every": KT_EVERY, "kernel_s_mean": t_kernel, "kernel_s_min": k_min, "kernel_s_max": k_max,
+             "s_per_step": (launches / steps_fp64) * (t_kernel or 0.0)}
+        if flops is None or not t_kernel:
+            return e
+        ach_tf = flops / t_kernel / 1e12
+        ach_gbs = bytes_ / t_kernel / 1e9
+        if bound == "hbm":
+            roof = {"bound": "hbm", "achieved": round(ach_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach_gbs / HBM_PEAK_GBS, 5)}
+        else:
+            roof = {"bound": "alu", "achieved": round(ach_tf, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach_tf / FP64_PEAK_TFLOPS, 5)}
+        roof.update({"traffic": measured_traffic(a.workload, kname, role)}, **e)
+        roof.update({"flop_per_launch": flops, "bytes_per_launch": bytes_,
+                     "tflops_achieved": round(ach_tf, 4), "tflops_frac": round(ach_tf / FP64_PEAK_TFLOPS, 5),
+                     "hbm_achieved_GBs": round(ach_gbs, 2), "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 5)})
+        return roof
+
+    # the Jacobian G~: algorithmic flops (bytes) per launch / mean duration of the timed launches
     if split:
         flops = SPLIT_FLOP_PER_CELL[s["dim"]] * n_cells
         bytes_ = BYTES_PER_DOF_F64[s["dim"]] * n_dofs + SPLIT_REC_BYTES_PER_CELL[s["dim"]] * n_cells
     else:
         flops = FLOP_PER_CELL[(s["dim"], s["degree"])] * n_cells
         bytes_ = BYTES_PER_DOF_F64[s["dim"]] * n_dofs
-    # achieved: algorithmic flops (bytes) per launch / mean duration of the launches in the timed region
-    k_count, k_mean, k_min, k_max = kt
-    t_kernel = k_mean if k_count > 0 else t_apply
-    ach_tf = flops / t_kernel / 1e12
-    ach_gbs = bytes_ / t_kernel / 1e9
-    variant = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 0)[0]
-    kname = kernel_name(s["dim"], s["degree"], variant, split)
-    if split:
-        # the records make the split apply HBM-bound (flop/B below the FP64 ridge of 9.8)
-        roof = {"bound": "hbm", "achieved": round(ach_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach_gbs / HBM_PEAK_GBS, 5)}
+    vj = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 0)[0]
+    # the records make the split apply HBM-bound (flop/B below the FP64 ridge of 9.8)
+    jac = kernel_entry(pff.PF_KTIME_JACOBIAN, flops, bytes_, "hbm" if split else "alu",
+                       kernel_name(s["dim"], s["degree"], vj, split, 0), "apply", t_fallback=t_apply)
+    jac.update({"apply_call_s": t_apply, "apply_call_f32_s": t_apply32})
+    # the block operator B~: counted where it reads stored coefficients (unsplit Q1)
+    vb = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 1)[0]
+    if s["degree"] == 1 and not split:
+        bflops = BLOCK_FLOP_PER_CELL[s["dim"]] * n_cells
+        bbytes = BLOCK_BYTES_PER_NODE_F64[s["dim"]] * n_nodes + BLOCK_COEF_BYTES_PER_CELL[s["dim"]] * n_cells
+        # flop/B is near the FP64 ridge (9.8): the binding roof is the larger of the two times
+        bbound = "alu" if bflops / FP64_PEAK_TFLOPS / 1e12 >= bbytes / HBM_PEAK_GBS / 1e9 else "hbm"
     else:
-        roof = {"bound": "alu", "achieved": round(ach_tf, 4), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach_tf / FP64_PEAK_TFLOPS, 5)}
-    roof.update({"traffic": measured_traffic(a.workload, kname),
-                 "kernel": kname, "launches_timed": k_count, "kernel_s_mean": t_kernel, "kernel_s_min": k_min,
-                 "kernel_s_max": k_max, "flop_per_launch": flops, "bytes_per_launch": bytes_,
-                 "tflops_achieved": round(ach_tf, 4), "tflops_frac": round(ach_tf / FP64_PEAK_TFLOPS, 5),
-                 "hbm_achieved_GBs": round(ach_gbs, 2), "hbm_frac": round(ach_gbs / HBM_PEAK_GBS, 5),
-                 "apply_call_s": t_apply, "apply_call_f32_s": t_apply32})
+        bflops = bbytes = bbound = None
+    blk = kernel_entry(pff.PF_KTIME_BLOCK, bflops, bbytes, bbound,
+                       kernel_name(s["dim"], s["degree"], vb, split, 1), "block")
+    # the roofline entry is the kernel with the larger time per step among the counted ones
+    roof = jac
+    if "frac" in blk and blk["s_per_step"] > jac["s_per_step"]:
+        roof = blk
+    roof = dict(roof, role="block operator B~" if roof is blk else "Jacobian G~")
     # the PDAS loop to convergence (Algorithm 1 repeated until A_k = A_{k-1} and ||R~|| <= 1e-10)
     # from the same iterate, in the workload's V-cycle precision
     S.set_vcycle_precision(base_prec)
@@ -422,6 +469,7 @@ def main():
         "apply_dofs_per_s_fp32": n_dofs / t_apply32,
         "stage_s_fp64": {k: r64[-1][k] for k in ("t_residual_s", "t_setup_s", "t_solve_s")},
         "roofline": roof,
+        "kernels": {"jacobian": jac, "block": blk},
         "cpu_baseline": None,
         "pdas_loop": pdas_out,
         "quantities": quant,

@@ -309,16 +309,27 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
  * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
  * Q2 levels have one kernel and are skipped. */
 pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
-/* HIP-event timing of the finest-level FP64 Jacobian cell kernel (the dominant
- * kernel of a Newton step).  enable = 1 clears the record and, from then on,
- * brackets every such launch (pf_jacobian_apply on the finest level, the
- * FGMRES operator applies and true residuals of pf_newton_step) with two
- * events on the launch stream; the Pi_C start of y is outside the bracket.
- * At most 1024 launches are recorded per period.  Timing adds two event
- * records per launch; enable = 0 stops recording and keeps the record. */
-pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable);
-/* Number of recorded launches and their mean / min / max duration in seconds
- * (waits for the last recorded launch).  count = 0 gives zeros. */
+/* HIP-event timing of the finest-level FP64 cell kernels of a Newton step.
+ * enable is a combination of
+ *   PF_KTIME_JACOBIAN  the Jacobian G~ (pf_jacobian_apply on the finest level, the FGMRES
+ *                      operator applies, true residuals and smoother residuals), and
+ *   PF_KTIME_BLOCK     the block operator B~ (the Chebyshev smoother's operator, the
+ *                      eigenvalue CG, pf_block_apply on the finest level).
+ * A nonzero enable clears both records and, from then on, brackets every every-th
+ * such launch of each record (the 1st, (every+1)-th, ...; every in [1, 1e6]) with two
+ * events on the launch stream; the Pi_C start of y is outside the bracket.  At most
+ * 1024 launches are recorded per record and period.  A bracket delays the stream by
+ * a few microseconds (two event records), which a stride above 1 spreads thin;
+ * enable = 0 stops recording and keeps the records (every is then ignored). */
+#define PF_KTIME_JACOBIAN 1
+#define PF_KTIME_BLOCK 2
+pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable, int every);
+/* One record (op = PF_KTIME_JACOBIAN or PF_KTIME_BLOCK): the launches seen since it was
+ * cleared (bracketed or not), the number bracketed and their mean / min / max duration
+ * in seconds (waits for the last bracketed launch).  count = 0 gives zero durations. */
+pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* count, double* avg_s,
+                                  double* min_s, double* max_s);
+/* pf_get_kernel_timing_op with op = PF_KTIME_JACOBIAN. */
 pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s);
 /* Read / force the choice of one (level, prec, mode); variant -1 = size heuristic,
  * zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */

@@ -93,6 +93,7 @@ CellParams make_cell_params(const Geom& g, const Material& m) {
   cp.p = g.p;
   cp.split = m.split;
   cp.qpd = nullptr;
+  cp.qcb = nullptr;
   return cp;
 }
 

@@ -15,6 +15,11 @@
 // The cell work is split into a displacement part (test functions w:
 // g(phi~) sigma(du) : e(w)) and a phase-field part (test functions psi), each
 // sum-factorized with q1_math.h, which keeps the live register set small.
+//
+// The block operator B~ (the smoother's operator, applied far more often than
+// G~) reads its phase-field coefficient c_phi JxW per Gauss point from a
+// per-level array written once per linearization (k_q1_block_coef), so its
+// cells load neither U nor form the gradient of u; every B~ shape below does.
 #include "q1_cell.h"
 
 namespace pff {
@@ -51,6 +56,7 @@ __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, const T* __
   const bool cell_xy = cx >= 0 && cx < cp.N[0] && cy >= 0 && cy < cp.N[1] &&
                        !cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1]);
   const Consts<T> kc(cp, 8);
+  const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
   T carry[4] = {T(0), T(0), T(0), T(0)};
   for (int kz = z_lo - 1; kz < z_hi; ++kz) {
     const bool cell = cell_xy && kz >= 0 && kz < cp.N[2];
@@ -85,16 +91,28 @@ __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, const T* __
     for (int c = 0; c < 3; ++c) combine3<T, TX>(outu[c], carry[c], val[c], nc[c]);
     T outp[8];
     if (cell) {
-      T dp[8], uu[3][8], ph[8];
+      if constexpr (MODE == MODE_BLOCK) {
+        T dp[8], cq[8];
+        const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)kz * cp.N[0] * cp.N[1];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const T v = x[3 * nn + gi[a]];
-        dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+        for (int a = 0; a < 8; ++a) {
+          const T v = x[3 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          cq[a] = qcb[a * cp.n_cells + cid];
+        }
+        cell3_phi_stored<T>(kc, dp, cq, outp);
+      } else {
+        T dp[8], uu[3][8], ph[8];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) uu[c][a] = U[c * nn + gi[a]];
-        ph[a] = COUPLE ? U[3 * nn + gi[a]] : T(0);
+        for (int a = 0; a < 8; ++a) {
+          const T v = x[3 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uu[c][a] = U[c * nn + gi[a]];
+          ph[a] = COUPLE ? U[3 * nn + gi[a]] : T(0);
+        }
+        cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
       }
-      cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
     } else {
 #pragma unroll
       for (int a = 0; a < 8; ++a) outp[a] = T(0);
@@ -135,6 +153,7 @@ __global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, const T* __
   const bool own_x = i >= 1 && cx <= cp.nn[0] - 1;
   const bool cell_x = cx >= 0 && cx < cp.N[0];
   const Consts<T> kc(cp, 4);
+  const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
   T carry[3] = {T(0), T(0), T(0)};
   for (int ky = y_lo - 1; ky < y_hi; ++ky) {
     const bool cell = cell_x && ky >= 0 && ky < cp.N[1] && !cell_in_hole(cp.lshape, cx, ky, cp.N[0], cp.N[1]);
@@ -168,16 +187,28 @@ __global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, const T* __
     combine2<T>(outu[1], carry[1], val[1], nc[1]);
     T outp[4];
     if (cell) {
-      T dp[4], uu[2][4], ph[4];
+      if constexpr (MODE == MODE_BLOCK) {
+        T dp[4], cq[4];
+        const int64_t cid = (int64_t)cx + (int64_t)ky * cp.N[0];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const T v = x[2 * nn + gi[a]];
-        dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
-        uu[0][a] = U[gi[a]];
-        uu[1][a] = U[nn + gi[a]];
-        ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+        for (int a = 0; a < 4; ++a) {
+          const T v = x[2 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          cq[a] = qcb[a * cp.n_cells + cid];
+        }
+        cell2_phi_stored<T>(kc, dp, cq, outp);
+      } else {
+        T dp[4], uu[2][4], ph[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const T v = x[2 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          uu[0][a] = U[gi[a]];
+          uu[1][a] = U[nn + gi[a]];
+          ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+        }
+        cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
       }
-      cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
     } else {
 #pragma unroll
       for (int a = 0; a < 4; ++a) outp[a] = T(0);
@@ -197,6 +228,61 @@ __global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, const T* __
   }
 }
 
+// One Q1 cell of the block operator B~ with the phase-field coefficients stored per point
+// (qcb[q * n_cells + cid]); contributions added atomically on the free DoFs.  part: 0 = all
+// rows, 1 = displacement rows, 2 = phase-field rows.
+template <int D, typename T>
+__device__ __forceinline__ void q1_block_stored(const CellParams& cp, int64_t g0, int64_t cid,
+                                                const T* __restrict__ x, const T* __restrict__ phit,
+                                                const uint8_t* __restrict__ mask, const T* __restrict__ qcb,
+                                                T* __restrict__ y, int part) {
+  constexpr int NL = D == 2 ? 4 : 8;
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  int64_t gi[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (D == 3 ? (a >> 2) * sz : 0);
+  const Consts<T> kc(cp, NL);
+  uint8_t mk[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) mk[a] = mask[gi[a]];
+  if (part != 2) {
+    T du[D][NL], pt[NL], outu[D][NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      pt[a] = phit[gi[a]];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T v = x[c * nn + gi[a]];
+        du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+      }
+    }
+    if constexpr (D == 3)
+      cell3_u<T>(kc, du, pt, outu);
+    else
+      cell2_u<T>(kc, du, pt, outu);
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int a = 0; a < NL; ++a)
+        if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
+  }
+  if (part == 1) return;
+  T dp[NL], cq[NL], outp[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) {
+    const T v = x[D * nn + gi[a]];
+    dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+    cq[a] = qcb[a * cp.n_cells + cid];
+  }
+  if constexpr (D == 3)
+    cell3_phi_stored<T>(kc, dp, cq, outp);
+  else
+    cell2_phi_stored<T>(kc, dp, cq, outp);
+#pragma unroll
+  for (int a = 0; a < NL; ++a)
+    if (!(mk[a] & kMaskPhi)) atomicAdd(&y[D * nn + gi[a]], outp[a]);
+}
+
 // ----------------------------------------------------------------------------------- atomic variant
 // One thread per cell with the same sum-factorized cell math; contributions are
 // added with device atomics into y pre-set to Pi_C x.  No halo recompute, so it
@@ -214,6 +300,10 @@ __global__ __launch_bounds__(128) void k_q1_3d_atomic(CellParams cp, const T* __
   if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
   const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
   const int64_t g0 = (int64_t)cx + (int64_t)cy * sy + (int64_t)cz * sz;
+  if constexpr (MODE == MODE_BLOCK) {
+    q1_block_stored<3, T>(cp, g0, cid, x, phit, mask, (const T*)cp.qcb, y, 0);
+    return;
+  }
   int64_t gi[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (a >> 2) * sz;
@@ -266,6 +356,10 @@ __global__ __launch_bounds__(128) void k_q1_2d_atomic(CellParams cp, const T* __
   if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
   const int64_t nn = cp.n_nodes, sy = cp.ns[1];
   const int64_t g0 = (int64_t)cx + (int64_t)cy * sy;
+  if constexpr (MODE == MODE_BLOCK) {
+    q1_block_stored<2, T>(cp, g0, cid, x, phit, mask, (const T*)cp.qcb, y, 0);
+    return;
+  }
   int64_t gi[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) gi[a] = g0 + (a & 1) + (a >> 1) * sy;
@@ -305,7 +399,7 @@ __global__ __launch_bounds__(128) void k_q1_2d_atomic(CellParams cp, const T* __
 
 // ----------------------------------------------------------------------------------- 3D bricks
 // One 256-thread workgroup per brick of kBX x kBY x kBZ cells.  The brick's
-// (kBX+1)(kBY+1)(kBZ+1) nodes of x, U, phi~ and the mask are first copied to
+// (kBX+1)(kBY+1)(kBZ+1) nodes of x, U (Jacobian only), phi~ and the mask are first copied to
 // LDS with row-contiguous loads (each node value read from HBM once per
 // brick instead of once per adjacent cell), then every thread evaluates one
 // cell from LDS and scatters with atomics as the atomic variant does.  The
@@ -319,7 +413,7 @@ __global__ __launch_bounds__(256) void k_q1_3d_brick(CellParams cp, const T* __r
                                                      const T* __restrict__ U, const T* __restrict__ phit,
                                                      const uint8_t* __restrict__ mask, T* __restrict__ y) {
   constexpr bool COUPLE = (MODE == MODE_APPLY);
-  constexpr int NU = COUPLE ? 4 : 3;  // U components the cell reads
+  constexpr int NU = COUPLE ? 4 : 1;  // U components the cell reads (none for B~: stored coefficients)
   __shared__ T sx[4][kBN];
   __shared__ T sU[NU][kBN];
   __shared__ T sp[kBN];
@@ -337,8 +431,10 @@ __global__ __launch_bounds__(256) void k_q1_3d_brick(CellParams cp, const T* __r
     sp[t] = in ? phit[g] : T(0);
 #pragma unroll
     for (int c = 0; c < 4; ++c) sx[c][t] = in ? x[c * nn + g] : T(0);
+    if constexpr (COUPLE) {
 #pragma unroll
-    for (int c = 0; c < NU; ++c) sU[c][t] = in ? U[c * nn + g] : T(0);
+      for (int c = 0; c < NU; ++c) sU[c][t] = in ? U[c * nn + g] : T(0);
+    }
   }
   __syncthreads();
   const int lx = threadIdx.x % kBX, ly = (threadIdx.x / kBX) % kBY, lz = threadIdx.x / (kBX * kBY);
@@ -372,15 +468,26 @@ __global__ __launch_bounds__(256) void k_q1_3d_brick(CellParams cp, const T* __r
       for (int a = 0; a < 8; ++a)
         if (!(mk[a] & (1 << c))) atomicAdd(&y[c * nn + gi[a]], outu[c][a]);
   }
-  T dp[8], uu[3][8], ph[8], outp[8];
+  T dp[8], outp[8];
 #pragma unroll
-  for (int a = 0; a < 8; ++a) {
-    dp[a] = (mk[a] & kMaskPhi) ? T(0) : sx[3][li[a]];
+  for (int a = 0; a < 8; ++a) dp[a] = (mk[a] & kMaskPhi) ? T(0) : sx[3][li[a]];
+  if constexpr (COUPLE) {
+    T uu[3][8], ph[8];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) uu[c][a] = sU[c][li[a]];
-    ph[a] = COUPLE ? sU[NU - 1][li[a]] : T(0);
+    for (int a = 0; a < 8; ++a) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) uu[c][a] = sU[c][li[a]];
+      ph[a] = sU[3][li[a]];
+    }
+    cell3_phi<T, true>(kc, du, dp, uu, ph, outp);
+  } else {
+    const T* __restrict__ qcb = (const T*)cp.qcb;
+    const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)cz * cp.N[0] * cp.N[1];
+    T cq[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) cq[q] = qcb[q * cp.n_cells + cid];
+    cell3_phi_stored<T>(kc, dp, cq, outp);
   }
-  cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
 #pragma unroll
   for (int a = 0; a < 8; ++a)
     if (!(mk[a] & kMaskPhi)) atomicAdd(&y[3 * nn + gi[a]], outp[a]);
@@ -405,7 +512,10 @@ __global__ __launch_bounds__(128) void k_q1_split(CellParams cp, const T* __rest
   const int cz = D == 3 ? (int)(cid / ((int64_t)cp.N[0] * cp.N[1])) : 0;
   if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
   const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
-  q1_cell_atomic<D, T, COUPLE>(cp, g0, x, U, phit, mask, y, part);
+  if constexpr (MODE == MODE_BLOCK)
+    q1_block_stored<D, T>(cp, g0, cid, x, phit, mask, (const T*)cp.qcb, y, part);
+  else
+    q1_cell_atomic<D, T, COUPLE>(cp, g0, x, U, phit, mask, y, part);
 }
 
 // ----------------------------------------------------------------------------------- other modes
@@ -496,6 +606,64 @@ static pf_status launch_q1_aux(const Geom& g, const CellParams& cp, int mode, co
   return PF_OK;
 }
 
+// ----------------------------------------------------------------------------------- B~ coefficients
+// c[q * n_cells + cid] = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) JxW at Gauss point q of cell
+// cid, from the level's linearization point U (FP64), stored in FP64 and FP32; 0 in hole cells.
+template <int D>
+__global__ __launch_bounds__(128) void k_q1_block_coef(CellParams cp, const double* __restrict__ U,
+                                                       double* __restrict__ c64, float* __restrict__ c32) {
+  constexpr int NL = D == 3 ? 8 : 4;
+  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cid >= cp.n_cells) return;
+  const int cx = (int)(cid % cp.N[0]);
+  const int cy = (int)((cid / cp.N[0]) % cp.N[1]);
+  const int cz = D == 3 ? (int)(cid / ((int64_t)cp.N[0] * cp.N[1])) : 0;
+  double cph[NL];
+  if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) cph[q] = 0.0;
+  } else {
+    const int64_t nn = cp.n_nodes;
+    const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
+    double uu[D][NL], pt[NL], gw[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      const int64_t gi = g0 + (a & 1) + ((a >> 1) & 1) * cp.ns[1] + (D == 3 ? (a >> 2) * cp.ns[2] : 0);
+      pt[a] = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) uu[c][a] = U[c * nn + gi];
+    }
+    const Consts<double> kc(cp, NL);
+    if constexpr (D == 3)
+      cell3_diag_coef<double>(kc, uu, pt, gw, cph);
+    else
+      cell2_diag_coef<double>(kc, uu, pt, gw, cph);
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    c64[q * cp.n_cells + cid] = cph[q];
+    c32[q * cp.n_cells + cid] = (float)cph[q];
+  }
+}
+
+int q1_block_coef_values(int d) { return d == 3 ? 8 : 4; }
+
+pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U, double* c64, float* c32,
+                            hipStream_t s) {
+  if (g.p != 1 || !(g.d == 2 || g.d == 3) || !c64 || !c32) {
+    set_error("block coefficients: Q1 levels with coefficient storage only");
+    return PF_ERR_UNSUPPORTED;
+  }
+  if (g.n_cells == 0) return PF_OK;
+  const int64_t nb = (g.n_cells + 127) / 128;
+  if (g.d == 3)
+    k_q1_block_coef<3><<<nb, 128, 0, s>>>(cp, U, c64, c32);
+  else
+    k_q1_block_coef<2><<<nb, 128, 0, s>>>(cp, U, c64, c32);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
 // ----------------------------------------------------------------------------------- dispatch
 // Variant per level: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles, 2 = atomic,
 // 3 = LDS-staged bricks (3D; 2D maps it to 2), 4 = split cells (two work items per cell).
@@ -537,6 +705,10 @@ bool q1_tiled_handles(const Geom& g, int mode, int requested) {
 template <typename T>
 static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                            const uint8_t* mask, T* y, hipStream_t s) {
+  if (mode == MODE_BLOCK && !cp.qcb) {
+    set_error("Q1 block operator: the level's stored coefficients are missing");
+    return PF_ERR_UNSUPPORTED;
+  }
   const int variant = q1_variant(g, mode, cp.variant);
   if (variant == 4) {
     const int64_t nb = (2 * ((g.n_cells + 63) / 64) * 64 + 127) / 128;

@@ -74,6 +74,7 @@ struct CellParams {
   int d, p;            // dimension and degree
   int split;           // PF_SPLIT_NONE or PF_SPLIT_MIEHE (Sec. 2.1)
   const void* qpd;     // split: the level's per-point eigen-records in the apply's precision (or null)
+  const void* qcb;     // Q1 block operator: per-point c_phi JxW of the level in the apply's precision (or null)
 };
 
 // Material constants (Sec. 2.1): mu, lambda from E, nu; G_c, eps, kappa, p; energy split.
@@ -106,6 +107,10 @@ pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x,
 // Miehe split on Q1 levels (cell_split.hip): records of the per-point eigen-data
 // (split_record_values(d) values per cell), computed from the level's U
 int split_record_values(int d);
+// Q1 block operator coefficients: values per cell, and the per-linearization pass that writes them
+int q1_block_coef_values(int d);
+pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U, double* c64, float* c32,
+                            hipStream_t s);
 pf_status launch_split_data(const Geom& g, const CellParams& cp, const double* U, double* rec64, float* rec32,
                             hipStream_t s);
 

@@ -216,6 +216,49 @@ __device__ __forceinline__ void cell2_phi(const Consts<T>& k, const T du[2][4], 
   grad2T(Gp, k.ih, out);
 }
 
+// ----------------------------------------------------------------------------------- stored coefficients
+// Phase-field rows of the block operator B~ (no phi-u coupling) from per-point coefficients
+// fixed by the linearization point: cq[q] = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) JxW at
+// Gauss point q (the same c_phi as cell3_phi / cell2_phi).  out[a] = sum_q cq[q] dphi(q)
+// N_a(q) + the gradient term of cell3_phi / cell2_phi.
+template <typename T>
+__device__ __forceinline__ void cell3_phi_stored(const Consts<T>& k, const T dp[8], const T cq[8], T out[8]) {
+  T dv[8];
+  val3(dp, dv);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) dv[q] *= cq[q];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) out[a] = T(0);
+  val3T(dv, out);
+  T Gp[3][4];
+  grad3(dp, k.ih, Gp);
+  const T s = T(2) * k.gcx * k.jxw;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gp[j][r] *= s;
+  grad3T(Gp, k.ih, out);
+}
+
+template <typename T>
+__device__ __forceinline__ void cell2_phi_stored(const Consts<T>& k, const T dp[4], const T cq[4], T out[4]) {
+  T dv[4];
+  val2(dp, dv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dv[q] *= cq[q];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) out[a] = T(0);
+  val2T(dv, out);
+  T Gp[2][2];
+  grad2(dp, k.ih, Gp);
+  const T s = T(2) * k.gcx * k.jxw;
+  Gp[0][0] *= s;
+  Gp[0][1] *= s;
+  Gp[1][0] *= s;
+  Gp[1][1] *= s;
+  grad2T(Gp, k.ih, out);
+}
+
 // ----------------------------------------------------------------------------------- residual
 // -A(U) on one cell (Sec. 2.3): displacement rows -(g(phi~) sigma(u) + phi~^2 p I) : grad(N_a e_c);
 // phase-field rows -[((1-kappa) phi E_s + 2 phi p div u - G_c/eps (1 - phi)) N_a

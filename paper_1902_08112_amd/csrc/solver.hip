@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <limits>
 #include <vector>
 
 #include "common.h"
@@ -165,6 +166,9 @@ struct LevelBuf {
   float *U32 = nullptr, *phit32 = nullptr, *diag32 = nullptr;
   double* rec64 = nullptr;  // split: per-point eigen-records of U (Q1 levels), FP64 and FP32
   float* rec32 = nullptr;
+  double* cb64 = nullptr;   // Q1 without the split: per-point c_phi JxW of B~, FP64 and FP32
+  float* cb32 = nullptr;
+  double cb_pres = std::numeric_limits<double>::quiet_NaN();  // pressure the coefficients hold
   uint8_t *base = nullptr, *mask = nullptr;
   void *vb = nullptr, *vx = nullptr, *vr = nullptr, *vt = nullptr, *vd = nullptr;
   double eig[4] = {1, 1, 1, 1};
@@ -199,10 +203,13 @@ struct pf_ctx {
   double* part_lev = nullptr;
   double* qpart = nullptr;      // reduction scratch of the quantities of interest
   double* host_scal = nullptr;  // pinned host copy of the FGMRES scalars (kHostScal doubles)
-  // optional HIP-event timing of the finest-level FP64 Jacobian cell kernel (pf_set_kernel_timing)
-  bool ktime_on = false;
-  int ktime_n = 0;
-  std::vector<hipEvent_t> ktime_ev;  // pairs (start, end), kKernelTimerMax of them
+  // optional HIP-event timing of the finest-level FP64 cell kernels (pf_set_kernel_timing):
+  // record 0 = Jacobian G~, record 1 = block operator B~
+  int ktime_mask = 0;
+  int ktime_every = 1;            // bracket every ktime_every-th launch of a record
+  int64_t ktime_seen[2] = {0, 0};  // launches seen since the record was cleared
+  int ktime_n[2] = {0, 0};
+  std::vector<hipEvent_t> ktime_ev[2];  // pairs (start, end), kKernelTimerMax of them per record
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
@@ -230,7 +237,8 @@ struct pf_ctx {
     for (hipEvent_t e : aux_ev) hipEventDestroy(e);
     if (fork_ev) hipEventDestroy(fork_ev);
     if (host_scal) hipHostFree(host_scal);
-    for (hipEvent_t e : ktime_ev) hipEventDestroy(e);
+    for (int k = 0; k < 2; ++k)
+      for (hipEvent_t e : ktime_ev[k]) hipEventDestroy(e);
   }
   bool has_extra = false, has_lin = false;
   size_t ws_bytes = 0;
@@ -409,6 +417,11 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
       b.rec64 = cv.take<double>(nr);
       b.rec32 = cv.take<float>(nr);
     }
+    if (o.stress_split == PF_SPLIT_NONE && b.g.p == 1) {
+      const size_t nq = (size_t)q1_block_coef_values(b.g.d) * (size_t)b.g.n_cells;
+      b.cb64 = cv.take<double>(nq);
+      b.cb32 = cv.take<float>(nq);
+    }
   }
   const Geom& gf = lev[L - 1].g;
   const size_t nn = gf.n_nodes, nd = gf.n_dofs;
@@ -480,8 +493,18 @@ CellParams level_params(pf_ctx* c, int l, int prec, int mode) {
     cp.variant = b.variant[pi][mi];
     cp.zc = b.zc[pi][mi];
     if (cp.split) cp.qpd = prec == PF_F64 ? (const void*)b.rec64 : (const void*)b.rec32;
+    if (mode == MODE_BLOCK && b.cb64) cp.qcb = prec == PF_F64 ? (const void*)b.cb64 : (const void*)b.cb32;
   }
   return cp;
+}
+
+// the per-point coefficients of B~ on a Q1 level from its linearization point and the current pressure
+pf_status refresh_block_coef(pf_ctx* c, int l, hipStream_t s) {
+  LevelBuf& b = c->lev[l];
+  if (!b.cb64) return PF_OK;
+  PFF_TRY(launch_block_coef(b.g, cparams(c, l), b.U, b.cb64, b.cb32, s));
+  b.cb_pres = c->mat.p;
+  return PF_OK;
 }
 
 // whether the (level, prec, mode) operator starts from y = Pi_C x written by a separate pass
@@ -494,13 +517,16 @@ bool apply_needs_preset(pf_ctx* c, int l, int prec, int mode) {
 pf_status level_apply(pf_ctx* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s,
                       bool y_preset = false) {
   LevelBuf& b = c->lev[l];
+  // a pressure set since the linearization reaches B~ through its coefficients
+  if (mode == MODE_BLOCK && b.cb64 && !(b.cb_pres == c->mat.p)) PFF_TRY(refresh_block_coef(c, l, s));
   const CellParams cp = level_params(c, l, prec, mode);
-  if (c->ktime_on && prec == PF_F64 && mode == MODE_APPLY && l == (int)c->lev.size() - 1 &&
-      c->ktime_n < kKernelTimerMax) {
+  const int kop = mode == MODE_APPLY ? 0 : (mode == MODE_BLOCK ? 1 : -1);
+  if (kop >= 0 && ((c->ktime_mask >> kop) & 1) && prec == PF_F64 && l == (int)c->lev.size() - 1 &&
+      c->ktime_seen[kop]++ % c->ktime_every == 0 && c->ktime_n[kop] < kKernelTimerMax) {
     // the Pi_C start (when needed) outside, the cell kernel alone between the two events
     if (!y_preset && !tiled_writes_all(b.g, cp, mode))
       PFF_TRY(vec_init_constrained<double>((double*)y, (const double*)x, b.mask, b.g.n_nodes, b.g.d, s));
-    hipEvent_t* ev = &c->ktime_ev[2 * c->ktime_n++];
+    hipEvent_t* ev = &c->ktime_ev[kop][2 * c->ktime_n[kop]++];
     PFF_HIP(hipEventRecord(ev[0], s));
     PFF_TRY(launch_cell<double>(b.g, cp, mode, (const double*)x, b.U, b.phit, b.mask, (double*)y, s));
     PFF_HIP(hipEventRecord(ev[1], s));
@@ -796,10 +822,12 @@ pf_status ensure_aux(pf_ctx* c) {
   return PF_OK;
 }
 
-// per-level set-up task: split eigen-records, diagonal of B~, FP32 copies, eigenvalue CG
+// per-level set-up task: split eigen-records or B~ coefficients, diagonal of B~, FP32 copies,
+// eigenvalue CG
 pf_status level_task(pf_ctx* c, int l, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   if (b.rec64) PFF_TRY(launch_split_data(b.g, cparams(c, l), b.U, b.rec64, b.rec32, s));
+  PFF_TRY(refresh_block_coef(c, l, s));
   PFF_TRY(apply_op<double>(b.g, cparams(c, l), MODE_DIAG, nullptr, b.U, b.phit, b.mask, b.diag, s));
   PFF_TRY(vec_cast<double, float>(b.U32, b.U, b.g.n_dofs, s));
   PFF_TRY(vec_cast<double, float>(b.phit32, b.phit, b.g.n_nodes, s));
@@ -1131,38 +1159,62 @@ pf_status pf_jacobian_apply(pf_ctx* ctx, int level, int prec, const void* d_x, v
   return apply_entry(ctx, level, prec, MODE_APPLY, d_x, d_y, stream);
 }
 
-pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable) {
+pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable, int every) {
   NEED_CTX();
-  if (enable && ctx->ktime_ev.empty()) {
-    ctx->ktime_ev.resize(2 * kKernelTimerMax, nullptr);
-    for (auto& e : ctx->ktime_ev) PFF_HIP(hipEventCreate(&e));
+  if (enable < 0 || enable > (PF_KTIME_JACOBIAN | PF_KTIME_BLOCK)) {
+    set_error("enable must be 0 or a combination of PF_KTIME_JACOBIAN and PF_KTIME_BLOCK");
+    return PF_ERR_INVALID_ARG;
   }
-  ctx->ktime_on = enable != 0;
-  if (enable) ctx->ktime_n = 0;
+  if (every < 1 || every > 1000000) {
+    set_error("every must be in [1, 1000000]");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < 2 && enable; ++k)
+    if (((enable >> k) & 1) && ctx->ktime_ev[k].empty()) {
+      ctx->ktime_ev[k].resize(2 * kKernelTimerMax, nullptr);
+      for (auto& e : ctx->ktime_ev[k]) PFF_HIP(hipEventCreate(&e));
+    }
+  ctx->ktime_mask = enable;
+  if (enable) {
+    ctx->ktime_every = every;
+    for (int k = 0; k < 2; ++k) ctx->ktime_n[k] = 0, ctx->ktime_seen[k] = 0;
+  }
   return PF_OK;
 }
 
-pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s) {
+pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* count, double* avg_s, double* min_s,
+                                  double* max_s) {
   NEED_CTX();
-  if (!count || !avg_s || !min_s || !max_s) {
-    set_error("count, avg_s, min_s and max_s must be non-NULL");
+  if (!launches || !count || !avg_s || !min_s || !max_s) {
+    set_error("launches, count, avg_s, min_s and max_s must be non-NULL");
     return PF_ERR_INVALID_ARG;
   }
+  if (op != PF_KTIME_JACOBIAN && op != PF_KTIME_BLOCK) {
+    set_error("op must be PF_KTIME_JACOBIAN or PF_KTIME_BLOCK");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int k = op == PF_KTIME_JACOBIAN ? 0 : 1;
   double sum = 0.0, lo = 0.0, hi = 0.0;
-  for (int i = 0; i < ctx->ktime_n; ++i) {
-    PFF_HIP(hipEventSynchronize(ctx->ktime_ev[2 * i + 1]));
+  for (int i = 0; i < ctx->ktime_n[k]; ++i) {
+    PFF_HIP(hipEventSynchronize(ctx->ktime_ev[k][2 * i + 1]));
     float ms = 0.f;
-    PFF_HIP(hipEventElapsedTime(&ms, ctx->ktime_ev[2 * i], ctx->ktime_ev[2 * i + 1]));
+    PFF_HIP(hipEventElapsedTime(&ms, ctx->ktime_ev[k][2 * i], ctx->ktime_ev[k][2 * i + 1]));
     const double t = 1e-3 * ms;
     sum += t;
     lo = i ? std::min(lo, t) : t;
     hi = i ? std::max(hi, t) : t;
   }
-  *count = ctx->ktime_n;
-  *avg_s = ctx->ktime_n ? sum / ctx->ktime_n : 0.0;
+  *launches = ctx->ktime_seen[k];
+  *count = ctx->ktime_n[k];
+  *avg_s = ctx->ktime_n[k] ? sum / ctx->ktime_n[k] : 0.0;
   *min_s = lo;
   *max_s = hi;
   return PF_OK;
+}
+
+pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s) {
+  int64_t launches = 0;
+  return pf_get_kernel_timing_op(ctx, PF_KTIME_JACOBIAN, &launches, count, avg_s, min_s, max_s);
 }
 
 pf_status pf_block_apply(pf_ctx* ctx, int level, int prec, const void* d_x, void* d_y, void* stream) {

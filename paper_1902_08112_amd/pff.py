@@ -22,6 +22,7 @@ PF_F64, PF_F32 = 0, 1
 PF_PREC_FULL, PF_PREC_DIAG = 0, 1
 PF_SPLIT_NONE, PF_SPLIT_MIEHE = 0, 1
 PF_COARSE_AUTO, PF_COARSE_FUSED, PF_COARSE_STEPS = 0, 1, 2
+PF_KTIME_JACOBIAN, PF_KTIME_BLOCK = 1, 2
 PF_BOX, PF_LSHAPE = 0, 1
 PF_MASK_PHI = 8
 
@@ -98,13 +99,15 @@ SIGNATURES = {
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
-    "pf_set_kernel_timing": (I, [VP, I]),
+    "pf_set_kernel_timing": (I, [VP, I, I]),
     "pf_pdas_solve": (I, [VP, VP, VP, VP, I, D, C.POINTER(PdasReport), VP]),
     "pf_extrapolate": (I, [VP, VP, VP, D, VP, VP]),
     "pf_set_pressure": (I, [VP, D]),
     "pf_energies": (I, [VP, VP, C.POINTER(D), VP]),
     "pf_boundary_traction": (I, [VP, VP, I, C.POINTER(D), VP]),
     "pf_get_kernel_timing": (I, [VP, C.POINTER(I), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
+    "pf_get_kernel_timing_op": (I, [VP, I, C.POINTER(C.c_int64), C.POINTER(I), C.POINTER(D), C.POINTER(D),
+                                    C.POINTER(D)]),
     "pf_batch_workspace_size": (I, [C.POINTER(Mesh), I, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "pf_batch_setup": (I, [C.POINTER(Mesh), C.POINTER(D), I, C.POINTER(Options), VP, C.c_size_t, VP,
                            C.POINTER(VP)]),
@@ -496,23 +499,28 @@ class Solver:
         """PF_COARSE_AUTO (dense matrix of the coarse solve when small), PF_COARSE_FUSED or PF_COARSE_STEPS."""
         _check(lib().pf_set_coarse_mode(self.ctx, mode), "pf_set_coarse_mode")
 
-    def set_kernel_timing(self, enable):
-        """Bracket every finest-level FP64 Jacobian cell kernel with HIP events (see pff.h)."""
-        _check(lib().pf_set_kernel_timing(self.ctx, 1 if enable else 0), "pf_set_kernel_timing")
+    def set_kernel_timing(self, enable, every=1):
+        """Bracket the finest-level FP64 cell kernels with HIP events (see pff.h): True or
+        PF_KTIME_JACOBIAN for G~, PF_KTIME_BLOCK for B~, or both OR-ed; False stops.
+        every > 1 brackets every every-th launch of each record."""
+        mask = PF_KTIME_JACOBIAN if enable is True else int(enable)
+        _check(lib().pf_set_kernel_timing(self.ctx, mask, every), "pf_set_kernel_timing")
 
-    def kernel_timing(self):
-        """(count, mean_s, min_s, max_s) of the launches recorded since timing was enabled."""
-        n, a, lo, hi = I(0), D(0), D(0), D(0)
-        _check(lib().pf_get_kernel_timing(self.ctx, C.byref(n), C.byref(a), C.byref(lo), C.byref(hi)),
-               "pf_get_kernel_timing")
-        return n.value, a.value, lo.value, hi.value
+    def kernel_timing(self, op=PF_KTIME_JACOBIAN, launches=False):
+        """(count, mean_s, min_s, max_s) of the bracketed launches of one record since timing
+        was enabled; with launches=True, (launches seen, count, mean_s, min_s, max_s)."""
+        seen, n, a, lo, hi = C.c_int64(0), I(0), D(0), D(0), D(0)
+        _check(lib().pf_get_kernel_timing_op(self.ctx, op, C.byref(seen), C.byref(n), C.byref(a), C.byref(lo),
+                                             C.byref(hi)), "pf_get_kernel_timing_op")
+        r = (n.value, a.value, lo.value, hi.value)
+        return (seen.value,) + r if launches else r
 
     # autotuner ---------------------------------------------------------------
     def tuning_key(self):
         m = self.mesh
         arch = self.torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
         return (f"{arch}|d{m.dim}p{m.degree}|{m.n_cells[0]}x{m.n_cells[1]}x{m.n_cells[2]}|dom{m.domain}"
-                f"|L{m.n_levels}")
+                f"|L{m.n_levels}|split{self.opt.stress_split}")
 
     def autotune(self, reps=20, cache_path=None):
         """Pick the fastest Q1 cell-loop shape per level (needs a linearization point).

@@ -69,9 +69,71 @@ def test_apply_every_kernel_variant(name):
             y = host(S.jacobian_apply(l, dev(x)))
             yb = host(S.block_apply(l, dev(x)))
             y32 = host(S.jacobian_apply(l, dev(x).to(torch.float32))).astype(np.float64)
-            e, eb, e32 = rel_err(y, refG), rel_err(yb, refB), rel_err(y32, refG)
-            print(f"  level {l} variant {v} zc {zc}: {e:.1e} {eb:.1e} {e32:.1e}", flush=True)
-            assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6
+            yb32 = host(S.block_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+            e, eb, e32, eb32 = rel_err(y, refG), rel_err(yb, refB), rel_err(y32, refG), rel_err(yb32, refB)
+            print(f"  level {l} variant {v} zc {zc}: {e:.1e} {eb:.1e} FP32 {e32:.1e} {eb32:.1e}", flush=True)
+            assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6 and eb32 <= 2e-6
+
+
+@pytest.mark.parametrize("name", ["small2d", "small3d", "small_lshape"])
+def test_block_apply_follows_pressure(name):
+    """B~ on Q1 levels reads its phase-field coefficient (which holds 2 p div u) from a per-level
+    array written at the linearization; a pressure set afterwards reaches the next apply, in
+    every shape and both precisions, as it reaches G~."""
+    from paper_1902_08112_amd import pff
+    s, U, phit, act, H, S = setup_case(name, seed=37)
+    torch = __import__("torch")
+    p2 = 100.0 * s["material"]["pressure"] + 0.1
+    s2 = dict(s, material=dict(s["material"], pressure=p2))
+    H2 = oracle_hierarchy(s2)
+    H2.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+    S.set_pressure(p2)
+    variants = [(2, -1), (4, -1), (0, 4)] + ([(3, -1), (1, 4)] if s["dim"] == 3 else [])
+    for l in range(s["n_levels"]):
+        x = np.random.default_rng(400 + l).uniform(-1, 1, H.levels[l].n_dofs)
+        refG, refB, oldB = H2.mg[l].G @ x, H2.mg[l].B @ x, H.mg[l].B @ x
+        nd = s["dim"] * H.levels[l].n_nodes
+        # the pressure moves B~ far beyond the FP64 bar on this state (a stale coefficient fails)
+        assert rel_err(refB[nd:], oldB[nd:]) > 1e-8
+        for v, zc in variants:
+            for mode in (0, 1):
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F64, mode, v, zc)
+                pff.pf_set_tuning(S.ctx, l, pff.PF_F32, mode, v, zc)
+            yb = host(S.block_apply(l, dev(x)))
+            yb32 = host(S.block_apply(l, dev(x).to(torch.float32))).astype(np.float64)
+            y = host(S.jacobian_apply(l, dev(x)))
+            e, eb, eb32 = rel_err(y, refG), rel_err(yb, refB), rel_err(yb32, refB)
+            print(f"  level {l} variant {v} zc {zc}: G {e:.1e} B {eb:.1e} B FP32 {eb32:.1e}", flush=True)
+            assert e <= 1e-12 and eb <= 1e-12 and eb32 <= 2e-6
+
+
+def test_kernel_timing_records():
+    """pf_set_kernel_timing brackets the finest-level FP64 launches of G~ and of B~ in a Newton
+    step (all, or every k-th); the records count what they saw and what they timed, and bad
+    arguments fail before anything is recorded."""
+    from paper_1902_08112_amd import pff
+    s = W.config("small3d")
+    print("[case] kernel timing small3d", flush=True)
+    U, Uold, phit = W.make_state(s)
+    S = gpu_solver(s)
+    S.set_vcycle_precision(pff.PF_F64)
+    for every in (1, 3):
+        S.set_kernel_timing(pff.PF_KTIME_JACOBIAN | pff.PF_KTIME_BLOCK, every=every)
+        S.newton_step(dev(U), dev(Uold), dev(phit))
+        S.set_kernel_timing(False)
+        for op in (pff.PF_KTIME_JACOBIAN, pff.PF_KTIME_BLOCK):
+            seen, n, mean, lo, hi = S.kernel_timing(op, launches=True)
+            print(f"  every {every} op {op}: {seen} launches, {n} timed, mean {mean * 1e6:.1f} us", flush=True)
+            assert seen > 0 and n == (seen + every - 1) // every
+            assert 0.0 < lo <= mean <= hi
+    # only the Jacobian record
+    S.set_kernel_timing(pff.PF_KTIME_JACOBIAN)
+    S.newton_step(dev(U), dev(Uold), dev(phit))
+    S.set_kernel_timing(False)
+    assert S.kernel_timing(pff.PF_KTIME_JACOBIAN)[0] > 0 and S.kernel_timing(pff.PF_KTIME_BLOCK)[0] == 0
+    for bad in (dict(enable=4), dict(enable=-1), dict(enable=1, every=0)):
+        with pytest.raises(pff.PffError):
+            S.set_kernel_timing(**bad)
 
 
 def test_autotune_report_and_cache(tmp_path):
