@@ -421,7 +421,7 @@ def main():
         Sd.set_constraints(torch.from_numpy(bits).cuda())
     run_steps(1, base_prec, Sd)
     if not a.no_tune:
-        Sd.autotune(reps=10)
+        Sd.autotune(reps=10, cache_path=a.tuning_cache)
     run_steps(a.warmup, base_prec, Sd)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -39,17 +39,34 @@ __device__ __forceinline__ void combine3(const T out[8], T carry, T& val, T& nca
   ncarry = y1;
 }
 
+// Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b to XCD b mod 8), each
+// XCD with its own L2.  xcd_tile maps b to a tile index so that every XCD receives one
+// contiguous range of tiles (a bijection of [0, nb) for any nb): tiles that share node
+// planes and columns then read them through the same L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t q = nb / kXcds, r = nb % kXcds;
+  const int64_t xcd = b % kXcds, k = b / kXcds;
+  return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// one wavefront per tile; tiles ordered z-chunk fastest, then x, then y (ntx x nty tiles of
+// TX x TY cells, nzc chunks), launched as a 1D grid of ntx * nty * nzc workgroups
 template <typename T, int MODE, int TX, int TY>
-__global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, const T* __restrict__ x,
+__global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, int nzc, const T* __restrict__ x,
                                               const T* __restrict__ U, const T* __restrict__ phit,
                                               const uint8_t* __restrict__ mask, T* __restrict__ y) {
   static_assert(TX * TY == 64, "one wavefront per tile");
   constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  const int bz = (int)(t % nzc);
+  const int bx = (int)((t / nzc) % ntx);
+  const int by = (int)(t / ((int64_t)nzc * ntx));
   const int lane = threadIdx.x;
   const int i = lane % TX, j = lane / TX;
-  const int cx = (int)blockIdx.x * (TX - 1) - 1 + i;
-  const int cy = (int)blockIdx.y * (TY - 1) - 1 + j;
-  const int z_lo = (int)blockIdx.z * zc;
+  const int cx = bx * (TX - 1) - 1 + i;
+  const int cy = by * (TY - 1) - 1 + j;
+  const int z_lo = bz * zc;
   const int z_hi = min(z_lo + zc, cp.nn[2]);
   const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
   const bool own_xy = i >= 1 && j >= 1 && cx <= cp.nn[0] - 1 && cy <= cp.nn[1] - 1;
@@ -756,17 +773,23 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
     const int tx = tile == 1 ? 16 : 8;
     const int64_t ntx = (g.nn[0] + tx - 2) / (tx - 1), nty = (g.nn[1] + 64 / tx - 2) / (64 / tx - 1);
     const int zc = q1_chunk(g, tile, cp.zc);
-    dim3 grid((unsigned)ntx, (unsigned)nty, (unsigned)((g.nn[2] + zc - 1) / zc));
+    const int nzc = (g.nn[2] + zc - 1) / zc;
+    const int64_t nb = ntx * nty * nzc;
+    if (nb > 0x7fffffff) {
+      set_error("Q1 marching tiles: too many tiles for one launch");
+      return PF_ERR_UNSUPPORTED;
+    }
+    const unsigned grid = (unsigned)nb;
     if (tile == 1) {
       if (mode == MODE_APPLY)
-        k_q1_3d<T, MODE_APPLY, 16, 4><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+        k_q1_3d<T, MODE_APPLY, 16, 4><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, nzc, x, U, phit, mask, y);
       else
-        k_q1_3d<T, MODE_BLOCK, 16, 4><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+        k_q1_3d<T, MODE_BLOCK, 16, 4><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, nzc, x, U, phit, mask, y);
     } else {
       if (mode == MODE_APPLY)
-        k_q1_3d<T, MODE_APPLY, 8, 8><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+        k_q1_3d<T, MODE_APPLY, 8, 8><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, nzc, x, U, phit, mask, y);
       else
-        k_q1_3d<T, MODE_BLOCK, 8, 8><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+        k_q1_3d<T, MODE_BLOCK, 8, 8><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, nzc, x, U, phit, mask, y);
     }
   } else {
     const int64_t ntx = (g.nn[0] + 62) / 63;

@@ -805,6 +805,16 @@ pf_status eig_readback(pf_ctx* c, hipStream_t s) {
   return PF_OK;
 }
 
+// the eigenvalue bounds of one level from its CG record (waits for stream s)
+pf_status eig_readback_level(pf_ctx* c, int l, hipStream_t s) {
+  if (c->lev[l].eig_fixed) return PF_OK;
+  EigDev h;
+  PFF_HIP(hipMemcpyAsync(&h, c->eigdev + l, sizeof(EigDev), hipMemcpyDeviceToHost, s));
+  PFF_HIP(hipStreamSynchronize(s));
+  eig_from_cg(h, c->lev[l].eig);
+  return PF_OK;
+}
+
 // helper streams and events of the level tasks (created on first use)
 pf_status ensure_aux(pf_ctx* c) {
   const size_t L = c->lev.size();
@@ -859,9 +869,16 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
     PFF_HIP(hipEventRecord(c->aux_ev[l], c->aux[l]));
   }
   PFF_TRY(level_task(c, L, s));
+  if (L > 0) {
+    // the dense coarse-solve matrix needs level 0 only: it is built on level 0's stream while
+    // the finest level's task (queued above) still runs
+    PFF_TRY(eig_readback_level(c, 0, c->aux[0]));
+    PFF_TRY(build_coarse_dense(c, c->aux[0]));
+    PFF_HIP(hipEventRecord(c->aux_ev[0], c->aux[0]));
+  }
   for (int l = 0; l < L; ++l) PFF_HIP(hipStreamWaitEvent(s, c->aux_ev[l], 0));
   PFF_TRY(eig_readback(c, s));
-  PFF_TRY(build_coarse_dense(c, s));
+  if (L == 0) PFF_TRY(build_coarse_dense(c, s));
   PFF_HIP(hipStreamSynchronize(s));
   c->has_lin = true;
   c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle
@@ -1577,8 +1594,9 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
 // Small chunks suit levels that barely fill the chip, long ones (fewer recomputed halo
 // layers) the large levels.
 static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {0, 32}, {0, 64},
-                               {1, 4}, {1, 8}, {1, 16}, {1, 32}};
-static const int kNCand = 12;
+                               {1, 4}, {1, 8}, {1, 16}, {1, 32}, {0, 2}, {0, 3}, {1, 2}};
+static const int kNCand = 15;
+static_assert(kNCand <= 16, "tune_us holds 16 candidates");
 static const double kTuneTie = 0.03;
 
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {

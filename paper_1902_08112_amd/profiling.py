@@ -81,16 +81,26 @@ def stats(a):
     lines = [f"# Kernel durations: {os.path.basename(a.out)}", "",
              "Command (from the repository root on the GPU box):", "", "```", a.command, "```", "",
              f"Kernel dispatches: {sum(len(v) for v in per.values())}, total kernel time {total * 1e3:.3f} ms.", ""]
-    if a.kernel:
-        sel = [(g, v) for (n, g), v in per_grid.items() if n == a.kernel and (a.grid is None or g == a.grid)]
-        for g, v in sel:
-            lines += [f"Dominant kernel `{a.kernel}` at grid {g}: {len(v)} dispatches, mean "
-                      f"{statistics.mean(v) * 1e6:.2f} us, median {statistics.median(v) * 1e6:.2f} us, "
+    for k, kname in enumerate(a.kernel or []):
+        # the finest level's launches: the largest grid of that kernel (or the one asked for)
+        grids = [g for (n, g) in per_grid if n == kname]
+        if not grids:
+            continue
+        g = a.grid if a.grid is not None else max(grids)
+        v = per_grid.get((kname, g), [])
+        if v:
+            lines += [f"{'Dominant kernel' if k == 0 else 'Kernel'} `{kname}` at grid {g}: {len(v)} dispatches, "
+                      f"mean {statistics.mean(v) * 1e6:.2f} us, median {statistics.median(v) * 1e6:.2f} us, "
                       f"min {min(v) * 1e6:.2f} us, max {max(v) * 1e6:.2f} us.", ""]
     lines += ["| kernel | calls | total ms | mean us | min us | max us | % |", "|---|---:|---:|---:|---:|---:|---:|"]
     for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:a.top]:
         lines.append(f"| `{name}` | {len(v)} | {sum(v) * 1e3:.3f} | {statistics.mean(v) * 1e6:.2f} | "
                      f"{min(v) * 1e6:.2f} | {max(v) * 1e6:.2f} | {100 * sum(v) / total:.1f} |")
+    lines += ["", "Per kernel and grid (the grid is the launch's total work-item count; one grid is one level):", "",
+              "| kernel | grid | calls | total ms | mean us | % |", "|---|---:|---:|---:|---:|---:|"]
+    for (name, g), v in sorted(per_grid.items(), key=lambda kv: -sum(kv[1]))[:a.top]:
+        lines.append(f"| `{name}` | {g} | {len(v)} | {sum(v) * 1e3:.3f} | {statistics.mean(v) * 1e6:.2f} | "
+                     f"{100 * sum(v) / total:.1f} |")
     with open(a.out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -140,7 +150,7 @@ def main(argv=None):
     s.add_argument("--trace", required=True)
     s.add_argument("--out", required=True)
     s.add_argument("--command", required=True)
-    s.add_argument("--kernel")
+    s.add_argument("--kernel", action="append", help="kernel name (repeatable; the first is the roofline kernel)")
     s.add_argument("--grid", type=int)
     s.add_argument("--top", type=int, default=25)
     t = sub.add_parser("traffic")
