@@ -15,8 +15,8 @@ and the smoother's block operator B~, with HIP events on the launch stream
 (pf_set_kernel_timing); "kernels" reports both (launches per step, mean launch
 duration, achieved = algorithmic flops or bytes per launch / mean duration),
 and the roofline entry is the one with the larger time per step among those
-with an algorithmic count (B~ is counted on unsplit Q1 levels, where it reads
-stored per-point coefficients).  traffic = HBM bytes per launch from the
+with an algorithmic count (B~ is counted without the split: on Q1 levels, where it reads
+stored per-point coefficients, and on 3D Q2).  traffic = HBM bytes per launch from the
 committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of this command
 (profiles/<workload>_apply_traffic.json for G~, _block_traffic.json for B~),
 while the kernel's sources are unchanged.  After the timed region a plain
@@ -50,13 +50,15 @@ BYTES_PER_DOF_F64 = {2: 8 * 3 + (8 + 1) / 3.0, 3: 8 * 3 + (8 + 1) / 4.0}
 # record bytes per cell (tr e, eigenvalues, eigenvectors: 8 values x 8 points 3D, 5 x 4 2D, FP64)
 SPLIT_FLOP_PER_CELL = {2: 656.0 + 4 * 76.0, 3: 2496.0 + 8 * 240.0}
 SPLIT_REC_BYTES_PER_CELL = {2: 5 * 4 * 8.0, 3: 8 * 8 * 8.0}
-# block operator B~ (the smoother's operator) on unsplit Q1 levels, which reads its phase-field
-# coefficient c_phi JxW per Gauss point: the same counting rule over the fields B~ touches
-# (forward (d+1)(I+Gr) + I, backward (d+1)(I+Gr), 36 flops per 3D and 21 per 2D point), and
-# x, y at d+1 values, phi~ and the mask per node plus 2^d FP64 coefficients per cell
-BLOCK_FLOP_PER_CELL = {2: 396.0, 3: 1512.0}
-BLOCK_BYTES_PER_NODE_F64 = {2: 8 * 6 + 8 + 1.0, 3: 8 * 8 + 8 + 1.0}
-BLOCK_COEF_BYTES_PER_CELL = {2: 4 * 8.0, 3: 8 * 8.0}
+# block operator B~ (the smoother's operator), same counting rule over the fields B~ touches.
+# Unsplit Q1 reads its phase-field coefficient c_phi JxW per Gauss point: forward (d+1)(I+Gr) + I,
+# backward (d+1)(I+Gr), 36 flops per 3D and 21 per 2D point; x, y at d+1 values, phi~ and the mask
+# per node plus 2^d FP64 coefficients per cell.  3D Q2 forms c_phi from the gradient of u on the
+# fly: forward (2d+1)(I+Gr) + I, backward (d+1)(I+Gr), 64 flops per point (the Jacobian's 96 less
+# the phi-u coupling); x, y at d+1 values, u at d values, phi~ and the mask per node.
+BLOCK_FLOP_PER_CELL = {(2, 1): 396.0, (3, 1): 1512.0, (3, 2): 11043.0}
+BLOCK_BYTES_PER_NODE_F64 = {(2, 1): 8 * 6 + 8 + 1.0, (3, 1): 8 * 8 + 8 + 1.0, (3, 2): 8 * 11 + 8 + 1.0}
+BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 0.0}
 # every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
 # timed FP64 steps (a bracket delays the stream by a few microseconds)
 KT_EVERY = 4
@@ -376,11 +378,12 @@ def main():
     jac = kernel_entry(pff.PF_KTIME_JACOBIAN, flops, bytes_, "hbm" if split else "alu",
                        kernel_name(s["dim"], s["degree"], vj, split, 0), "apply", t_fallback=t_apply)
     jac.update({"apply_call_s": t_apply, "apply_call_f32_s": t_apply32})
-    # the block operator B~: counted where it reads stored coefficients (unsplit Q1)
+    # the block operator B~ (counted without the split, on Q1 and 3D Q2)
     vb = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 1)[0]
-    if s["degree"] == 1 and not split:
-        bflops = BLOCK_FLOP_PER_CELL[s["dim"]] * n_cells
-        bbytes = BLOCK_BYTES_PER_NODE_F64[s["dim"]] * n_nodes + BLOCK_COEF_BYTES_PER_CELL[s["dim"]] * n_cells
+    key = (s["dim"], s["degree"])
+    if key in BLOCK_FLOP_PER_CELL and not split:
+        bflops = BLOCK_FLOP_PER_CELL[key] * n_cells
+        bbytes = BLOCK_BYTES_PER_NODE_F64[key] * n_nodes + BLOCK_COEF_BYTES_PER_CELL[key] * n_cells
         # flop/B is near the FP64 ridge (9.8): the binding roof is the larger of the two times
         bbound = "alu" if bflops / FP64_PEAK_TFLOPS / 1e12 >= bbytes / HBM_PEAK_GBS / 1e9 else "hbm"
     else:
