@@ -50,15 +50,16 @@ BYTES_PER_DOF_F64 = {2: 8 * 3 + (8 + 1) / 3.0, 3: 8 * 3 + (8 + 1) / 4.0}
 # record bytes per cell (tr e, eigenvalues, eigenvectors: 8 values x 8 points 3D, 5 x 4 2D, FP64)
 SPLIT_FLOP_PER_CELL = {2: 656.0 + 4 * 76.0, 3: 2496.0 + 8 * 240.0}
 SPLIT_REC_BYTES_PER_CELL = {2: 5 * 4 * 8.0, 3: 8 * 8 * 8.0}
-# block operator B~ (the smoother's operator), same counting rule over the fields B~ touches.
-# Unsplit Q1 reads its phase-field coefficient c_phi JxW per Gauss point: forward (d+1)(I+Gr) + I,
-# backward (d+1)(I+Gr), 36 flops per 3D and 21 per 2D point; x, y at d+1 values, phi~ and the mask
-# per node plus 2^d FP64 coefficients per cell.  3D Q2 forms c_phi from the gradient of u on the
-# fly: forward (2d+1)(I+Gr) + I, backward (d+1)(I+Gr), 64 flops per point (the Jacobian's 96 less
-# the phi-u coupling); x, y at d+1 values, u at d values, phi~ and the mask per node.
-BLOCK_FLOP_PER_CELL = {(2, 1): 396.0, (3, 1): 1512.0, (3, 2): 11043.0}
-BLOCK_BYTES_PER_NODE_F64 = {(2, 1): 8 * 6 + 8 + 1.0, (3, 1): 8 * 8 + 8 + 1.0, (3, 2): 8 * 11 + 8 + 1.0}
-BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 0.0}
+# block operator B~ (the smoother's operator), same counting rule over the fields B~ touches; its
+# per-point coefficients are stored at the linearization.  Q1 reads c_phi JxW per Gauss point:
+# forward (d+1)(I+Gr) + I, backward (d+1)(I+Gr), 36 flops per 3D and 21 per 2D point; x, y at d+1
+# values, phi~ and the mask per node plus 2^d FP64 coefficients per cell.  3D Q2 reads g(phi~) JxW
+# and c_phi: forward and backward (d+1)(I+Gr), 48 flops per point (the Jacobian's 96 less the phi-u
+# coupling and the linearization-point terms); x, y at d+1 values and the mask per node plus 54
+# FP64 coefficients per cell.
+BLOCK_FLOP_PER_CELL = {(2, 1): 396.0, (3, 1): 1512.0, (3, 2): 7776.0}
+BLOCK_BYTES_PER_NODE_F64 = {(2, 1): 8 * 6 + 8 + 1.0, (3, 1): 8 * 8 + 8 + 1.0, (3, 2): 8 * 8 + 1.0}
+BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 54 * 8.0}
 # every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
 # timed FP64 steps (a bracket delays the stream by a few microseconds)
 KT_EVERY = 4

@@ -162,10 +162,17 @@ __device__ __forceinline__ void q2_backward(Q2Lds<T>& L, const Q2Tab<T>& k, int 
 
 }  // namespace
 
+// Template-only mode: write the block operator's per-point coefficients g(phi~) JxW and c_phi
+// of the linearization point, [k][point][cell] with k = 0, 1 and point = x + 3 y + 9 z, to y
+// (FP64) instead of applying anything.
+constexpr int kModeQ2Coef = 17;
+
 // MODE: MODE_APPLY / MODE_BLOCK (masked direction, y pre-set to Pi_C x), MODE_RAW
 // (unmasked G x), MODE_RESID (-A(U); x unused), MODE_DIAG (diag G, every row; x unused).
 // The diagonal entry of node a is a sum over Gauss points of products of squared 1D
 // basis values / derivatives, i.e. the backward contraction with the tables B^2, D^2.
+// MODE_BLOCK reads g(phi~) JxW and c_phi per Gauss point from cp.qcb (kModeQ2Coef's
+// output) and loads neither phi~ nor U.
 template <typename T, int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_q2_3d(CellParams cp, const T* __restrict__ x, const T* __restrict__ U,
                                               const T* __restrict__ phit, const uint8_t* __restrict__ mask,
@@ -174,6 +181,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   constexpr bool kCouple = (MODE == MODE_APPLY || MODE == MODE_RAW);
   constexpr bool kResid = (MODE == MODE_RESID);
   constexpr bool kDiag = (MODE == MODE_DIAG);
+  constexpr bool kStored = (MODE == MODE_BLOCK);
+  constexpr bool kCoef = (MODE == kModeQ2Coef);
   __shared__ Q2Lds<T> L;
   const int tid = threadIdx.x;
   const int cs = tid / 9;  // 0 .. kQ2Cells (the last slot is the idle lane's)
@@ -208,62 +217,85 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
   // linearization point at the Gauss points: g(phi~), and the phase-field coefficients
   T col[3], tmp[3][3];
-  T pt[3];
-#pragma unroll
-  for (int az = 0; az < 3; ++az) col[az] = active ? phit[gi[az]] : T(0);
-  q2_forward<T, false>(L, k, cs, tx, ty, col, ih, pt, tmp);
+  T pt[3] = {T(0), T(0), T(0)};
   T phv[3], gphi[3][3];
-  if (kCouple || kResid) {
-#pragma unroll
-    for (int az = 0; az < 3; ++az) col[az] = active ? U[3 * nn + gi[az]] : T(0);
-    if (kResid)
-      q2_forward<T, true>(L, k, cs, tx, ty, col, ih, phv, gphi);
-    else
-      q2_forward<T, false>(L, k, cs, tx, ty, col, ih, phv, gphi);
-  }
-  T gu[3][3][3];  // [component][direction][qz]
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int az = 0; az < 3; ++az) col[az] = active ? U[c * nn + gi[az]] : T(0);
-    T v[3];
-    q2_forward<T, true>(L, k, cs, tx, ty, col, ih, v, gu[c]);
-  }
-  // per Gauss point: gdeg, cphi = (1-kappa) E_s + 2 p div u + G_c/eps, and the coupling
-  // tensor K = (1-kappa) phi sigma(u) + 2 p phi I (APPLY / RAW) or the residual terms
   T gdeg[3], cphi[3], Ksym[3][6], rf[3], rsu[3][6];
+  if constexpr (kStored) {
+    // g(phi~) JxW and c_phi of the thread's three Gauss points, written at the linearization
+    const T* qc = (const T*)cp.qcb;
+    const int64_t nc = cp.n_cells, q0 = tid % 9;
 #pragma unroll
-  for (int qz = 0; qz < 3; ++qz) {
-    const T e00 = gu[0][0][qz], e11 = gu[1][1][qz], e22 = gu[2][2][qz];
-    const T e01 = T(0.5) * (gu[0][1][qz] + gu[1][0][qz]);
-    const T e02 = T(0.5) * (gu[0][2][qz] + gu[2][0][qz]);
-    const T e12 = T(0.5) * (gu[1][2][qz] + gu[2][1][qz]);
-    const T tr = e00 + e11 + e22;
-    const T ee = e00 * e00 + e11 * e11 + e22 * e22 + T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
-    const T Es = T(0.5) * lam * tr * tr + mu * ee;
-    gdeg[qz] = (T(1) - kap) * pt[qz] * pt[qz] + kap;
-    cphi[qz] = (T(1) - kap) * Es + T(2) * pres * tr + gce;
-    const T s00 = T(2) * mu * e00 + lam * tr, s11 = T(2) * mu * e11 + lam * tr, s22 = T(2) * mu * e22 + lam * tr;
-    const T s01 = T(2) * mu * e01, s02 = T(2) * mu * e02, s12 = T(2) * mu * e12;
-    if (kCouple) {
-      const T a = (T(1) - kap) * phv[qz], b = T(2) * pres * phv[qz];
-      Ksym[qz][0] = a * s00 + b;
-      Ksym[qz][1] = a * s11 + b;
-      Ksym[qz][2] = a * s22 + b;
-      Ksym[qz][3] = a * s01;
-      Ksym[qz][4] = a * s02;
-      Ksym[qz][5] = a * s12;
+    for (int qz = 0; qz < 3; ++qz) {
+      gdeg[qz] = active ? qc[(q0 + 9 * qz) * nc + cid] : T(0);
+      cphi[qz] = active ? qc[(27 + q0 + 9 * qz) * nc + cid] : T(0);
     }
-    if (kResid) {
-      const T ph = phv[qz], p2 = pt[qz] * pt[qz] * pres;
-      rsu[qz][0] = -(gdeg[qz] * s00 + p2);
-      rsu[qz][1] = -(gdeg[qz] * s11 + p2);
-      rsu[qz][2] = -(gdeg[qz] * s22 + p2);
-      rsu[qz][3] = -gdeg[qz] * s01;
-      rsu[qz][4] = -gdeg[qz] * s02;
-      rsu[qz][5] = -gdeg[qz] * s12;
-      rf[qz] = -((T(1) - kap) * ph * Es + T(2) * ph * pres * tr - gce * (T(1) - ph));
+  } else {
+#pragma unroll
+    for (int az = 0; az < 3; ++az) col[az] = active ? phit[gi[az]] : T(0);
+    q2_forward<T, false>(L, k, cs, tx, ty, col, ih, pt, tmp);
+    if (kCouple || kResid) {
+#pragma unroll
+      for (int az = 0; az < 3; ++az) col[az] = active ? U[3 * nn + gi[az]] : T(0);
+      if (kResid)
+        q2_forward<T, true>(L, k, cs, tx, ty, col, ih, phv, gphi);
+      else
+        q2_forward<T, false>(L, k, cs, tx, ty, col, ih, phv, gphi);
     }
+    T gu[3][3][3];  // [component][direction][qz]
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int az = 0; az < 3; ++az) col[az] = active ? U[c * nn + gi[az]] : T(0);
+      T v[3];
+      q2_forward<T, true>(L, k, cs, tx, ty, col, ih, v, gu[c]);
+    }
+    // per Gauss point: gdeg, cphi = (1-kappa) E_s + 2 p div u + G_c/eps, and the coupling
+    // tensor K = (1-kappa) phi sigma(u) + 2 p phi I (APPLY / RAW) or the residual terms
+#pragma unroll
+    for (int qz = 0; qz < 3; ++qz) {
+      const T e00 = gu[0][0][qz], e11 = gu[1][1][qz], e22 = gu[2][2][qz];
+      const T e01 = T(0.5) * (gu[0][1][qz] + gu[1][0][qz]);
+      const T e02 = T(0.5) * (gu[0][2][qz] + gu[2][0][qz]);
+      const T e12 = T(0.5) * (gu[1][2][qz] + gu[2][1][qz]);
+      const T tr = e00 + e11 + e22;
+      const T ee = e00 * e00 + e11 * e11 + e22 * e22 + T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
+      const T Es = T(0.5) * lam * tr * tr + mu * ee;
+      gdeg[qz] = (T(1) - kap) * pt[qz] * pt[qz] + kap;
+      cphi[qz] = (T(1) - kap) * Es + T(2) * pres * tr + gce;
+      const T s00 = T(2) * mu * e00 + lam * tr, s11 = T(2) * mu * e11 + lam * tr, s22 = T(2) * mu * e22 + lam * tr;
+      const T s01 = T(2) * mu * e01, s02 = T(2) * mu * e02, s12 = T(2) * mu * e12;
+      if (kCouple) {
+        const T a = (T(1) - kap) * phv[qz], b = T(2) * pres * phv[qz];
+        Ksym[qz][0] = a * s00 + b;
+        Ksym[qz][1] = a * s11 + b;
+        Ksym[qz][2] = a * s22 + b;
+        Ksym[qz][3] = a * s01;
+        Ksym[qz][4] = a * s02;
+        Ksym[qz][5] = a * s12;
+      }
+      if (kResid) {
+        const T ph = phv[qz], p2 = pt[qz] * pt[qz] * pres;
+        rsu[qz][0] = -(gdeg[qz] * s00 + p2);
+        rsu[qz][1] = -(gdeg[qz] * s11 + p2);
+        rsu[qz][2] = -(gdeg[qz] * s22 + p2);
+        rsu[qz][3] = -gdeg[qz] * s01;
+        rsu[qz][4] = -gdeg[qz] * s02;
+        rsu[qz][5] = -gdeg[qz] * s12;
+        rf[qz] = -((T(1) - kap) * ph * Es + T(2) * ph * pres * tr - gce * (T(1) - ph));
+      }
+    }
+  }
+
+  if constexpr (kCoef) {
+    // the block operator's coefficients of this thread's Gauss points (every cell of the level)
+    const int64_t nc = cp.n_cells, q0 = tid % 9;
+    if (tid < 9 * kQ2Cells && cid < nc)
+#pragma unroll
+      for (int qz = 0; qz < 3; ++qz) {
+        y[(q0 + 9 * qz) * nc + cid] = gdeg[qz] * jxw[qz];
+        y[(27 + q0 + 9 * qz) * nc + cid] = cphi[qz];
+      }
+    return;
   }
 
   if constexpr (kDiag) {
@@ -315,7 +347,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     T (&Q)[3][8] = L.q[cs][tid % 9];
 #pragma unroll
     for (int qz = 0; qz < 3; ++qz) {
-      Q[qz][0] = gdeg[qz] * jxw[qz];
+      Q[qz][0] = kStored ? gdeg[qz] : gdeg[qz] * jxw[qz];
       Q[qz][1] = cphi[qz];
       if (kCouple)
 #pragma unroll
@@ -411,6 +443,10 @@ pf_status launch_cell_q2(const Geom& g, const CellParams& cp, int mode, const T*
   if (!(mode == MODE_APPLY || mode == MODE_BLOCK || (fp64 && (mode == MODE_RAW || mode == MODE_RESID || mode == MODE_DIAG))))
     return PF_OK;
   *handled = true;
+  if (mode == MODE_BLOCK && !cp.qcb) {
+    set_error("Q2 block operator: the level's stored coefficients are missing");
+    return PF_ERR_UNSUPPORTED;
+  }
   const int64_t nb = (g.n_cells + kQ2Cells - 1) / kQ2Cells;
   if (nb == 0) return PF_OK;
   switch (mode) {
@@ -432,6 +468,20 @@ pf_status launch_cell_q2(const Geom& g, const CellParams& cp, int mode, const T*
   }
   PFF_CHECK_LAUNCH();
   return PF_OK;
+}
+
+// the block operator's per-point coefficients of a 3D Q2 level: g(phi~) JxW and c_phi, FP64 and FP32
+pf_status launch_block_coef_q2(const Geom& g, const CellParams& cp, const double* U, const double* phit, double* c64,
+                               float* c32, hipStream_t s) {
+  if (g.d != 3 || g.p != 2 || !c64 || !c32) {
+    set_error("block coefficients: 3D Q2 levels with coefficient storage only");
+    return PF_ERR_UNSUPPORTED;
+  }
+  const int64_t nb = (g.n_cells + kQ2Cells - 1) / kQ2Cells;
+  if (nb == 0) return PF_OK;
+  k_q2_3d<double, kModeQ2Coef><<<nb, 64, 0, s>>>(cp, nullptr, U, phit, nullptr, c64);
+  PFF_CHECK_LAUNCH();
+  return vec_cast<double, float>(c32, c64, (int64_t)54 * g.n_cells, s);
 }
 
 pf_status launch_cell_q2_d(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,

@@ -111,6 +111,10 @@ int split_record_values(int d);
 int q1_block_coef_values(int d);
 pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U, double* c64, float* c32,
                             hipStream_t s);
+// 3D Q2 block operator coefficients: g(phi~) JxW and c_phi at the 27 Gauss points (54 values per cell)
+constexpr int kQ2BlockCoefValues = 54;
+pf_status launch_block_coef_q2(const Geom& g, const CellParams& cp, const double* U, const double* phit, double* c64,
+                               float* c32, hipStream_t s);
 pf_status launch_split_data(const Geom& g, const CellParams& cp, const double* U, double* rec64, float* rec32,
                             hipStream_t s);
 

@@ -166,7 +166,8 @@ struct LevelBuf {
   float *U32 = nullptr, *phit32 = nullptr, *diag32 = nullptr;
   double* rec64 = nullptr;  // split: per-point eigen-records of U (Q1 levels), FP64 and FP32
   float* rec32 = nullptr;
-  double* cb64 = nullptr;   // Q1 without the split: per-point c_phi JxW of B~, FP64 and FP32
+  double* cb64 = nullptr;   // without the split: B~'s per-point coefficients (Q1: c_phi JxW; 3D Q2:
+                            // g(phi~) JxW and c_phi), FP64 and FP32
   float* cb32 = nullptr;
   double cb_pres = std::numeric_limits<double>::quiet_NaN();  // pressure the coefficients hold
   uint8_t *base = nullptr, *mask = nullptr;
@@ -417,8 +418,9 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
       b.rec64 = cv.take<double>(nr);
       b.rec32 = cv.take<float>(nr);
     }
-    if (o.stress_split == PF_SPLIT_NONE && b.g.p == 1) {
-      const size_t nq = (size_t)q1_block_coef_values(b.g.d) * (size_t)b.g.n_cells;
+    if (o.stress_split == PF_SPLIT_NONE && (b.g.p == 1 || b.g.d == 3)) {
+      const size_t per = b.g.p == 1 ? (size_t)q1_block_coef_values(b.g.d) : (size_t)kQ2BlockCoefValues;
+      const size_t nq = per * (size_t)b.g.n_cells;
       b.cb64 = cv.take<double>(nq);
       b.cb32 = cv.take<float>(nq);
     }
@@ -498,11 +500,14 @@ CellParams level_params(pf_ctx* c, int l, int prec, int mode) {
   return cp;
 }
 
-// the per-point coefficients of B~ on a Q1 level from its linearization point and the current pressure
+// the per-point coefficients of B~ on a level from its linearization point and the current pressure
 pf_status refresh_block_coef(pf_ctx* c, int l, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   if (!b.cb64) return PF_OK;
-  PFF_TRY(launch_block_coef(b.g, cparams(c, l), b.U, b.cb64, b.cb32, s));
+  if (b.g.p == 1)
+    PFF_TRY(launch_block_coef(b.g, cparams(c, l), b.U, b.cb64, b.cb32, s));
+  else
+    PFF_TRY(launch_block_coef_q2(b.g, cparams(c, l), b.U, b.phit, b.cb64, b.cb32, s));
   b.cb_pres = c->mat.p;
   return PF_OK;
 }

@@ -75,11 +75,11 @@ def test_apply_every_kernel_variant(name):
             assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6 and eb32 <= 2e-6
 
 
-@pytest.mark.parametrize("name", ["small2d", "small3d", "small_lshape"])
+@pytest.mark.parametrize("name", ["small2d", "small3d", "small_lshape", "small3d_q2"])
 def test_block_apply_follows_pressure(name):
-    """B~ on Q1 levels reads its phase-field coefficient (which holds 2 p div u) from a per-level
-    array written at the linearization; a pressure set afterwards reaches the next apply, in
-    every shape and both precisions, as it reaches G~."""
+    """B~ on Q1 and 3D Q2 levels reads its phase-field coefficient (which holds 2 p div u) from a
+    per-level array written at the linearization; a pressure set afterwards reaches the next
+    apply, in every shape and both precisions, as it reaches G~."""
     from paper_1902_08112_amd import pff
     s, U, phit, act, H, S = setup_case(name, seed=37)
     torch = __import__("torch")
