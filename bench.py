@@ -63,11 +63,16 @@ BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 54 * 8.0}
 # every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
 # timed FP64 steps (a bracket delays the stream by a few microseconds)
 KT_EVERY = 4
+# a Chebyshev step fused into a marching-tile B~ apply (per DoF: r -= t, d' = c1 d + c2 r / diag,
+# x += d'; bytes: r read and written, diag, x read and written, d' written)
+CHEB_FLOP_PER_DOF = 7.0
+CHEB_BYTES_PER_DOF_F64 = 6 * 8.0
 
 
 # kernel of the finest-level FP64 Jacobian (mode 0) or block (mode 1) apply for a tuning variant,
 # as rocprofv3 names it
-def kernel_name(dim, degree, variant, split=False, mode=0):
+def kernel_name(dim, degree, variant, split=False, mode=0, fused=False):
+    fused = "true" if fused else "false"
     if split and degree == 1:
         return f"k_q1s<{dim}, double, {mode}, {1 if variant == 2 else 2}>"
     if degree == 2:
@@ -75,7 +80,7 @@ def kernel_name(dim, degree, variant, split=False, mode=0):
     if dim == 2:
         return {0: f"k_q1_2d<double, {mode}>", 2: f"k_q1_2d_atomic<double, {mode}>",
                 4: f"k_q1_split<2, double, {mode}>"}.get(variant, f"k_q1_2d<double, {mode}>")
-    return {0: f"k_q1_3d<double, {mode}, 8, 8>", 1: f"k_q1_3d<double, {mode}, 16, 4>",
+    return {0: f"k_q1_3d<double, {mode}, 8, 8, {fused}>", 1: f"k_q1_3d<double, {mode}, 16, 4, {fused}>",
             2: f"k_q1_3d_atomic<double, {mode}>", 3: f"k_q1_3d_brick<double, {mode}>",
             4: f"k_q1_split<3, double, {mode}>"}.get(variant, "?")
 
@@ -289,7 +294,7 @@ def main():
         # the FP64 steps also record the duration of every finest-level FP64 Jacobian cell
         # kernel launch with HIP events on the launch stream (the dominant kernel)
         if prec == pff.PF_F64:
-            S.set_kernel_timing(pff.PF_KTIME_JACOBIAN | pff.PF_KTIME_BLOCK, every=KT_EVERY)
+            S.set_kernel_timing(pff.PF_KTIME_JACOBIAN | pff.PF_KTIME_BLOCK | pff.PF_KTIME_BLOCK_CHEB, every=KT_EVERY)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         reps = run_steps(k, prec)
@@ -298,7 +303,8 @@ def main():
         kt = None
         if prec == pff.PF_F64:
             S.set_kernel_timing(False)
-            kt = {op: S.kernel_timing(op, launches=True) for op in (pff.PF_KTIME_JACOBIAN, pff.PF_KTIME_BLOCK)}
+            kt = {op: S.kernel_timing(op, launches=True)
+                  for op in (pff.PF_KTIME_JACOBIAN, pff.PF_KTIME_BLOCK, pff.PF_KTIME_BLOCK_CHEB)}
         return dt, reps, kt
 
     base_prec = pff.PF_F32 if s.get("vcycle") == "f32" else pff.PF_F64
@@ -391,11 +397,20 @@ def main():
         bflops = bbytes = bbound = None
     blk = kernel_entry(pff.PF_KTIME_BLOCK, bflops, bbytes, bbound,
                        kernel_name(s["dim"], s["degree"], vb, split, 1), "block")
-    # the roofline entry is the kernel with the larger time per step among the counted ones
-    roof = jac
-    if "frac" in blk and blk["s_per_step"] > jac["s_per_step"]:
-        roof = blk
-    roof = dict(roof, role="block operator B~" if roof is blk else "Jacobian G~")
+    kernels = {"jacobian": jac, "block": blk}
+    roles = {"jacobian": "Jacobian G~", "block": "block operator B~",
+             "block_cheb": "block operator B~ with a fused Chebyshev step"}
+    if kt[pff.PF_KTIME_BLOCK_CHEB][0] > 0 and bflops is not None:
+        cflops = bflops + CHEB_FLOP_PER_DOF * n_dofs
+        cbytes = bbytes + CHEB_BYTES_PER_DOF_F64 * n_dofs
+        cbound = "alu" if cflops / FP64_PEAK_TFLOPS / 1e12 >= cbytes / HBM_PEAK_GBS / 1e9 else "hbm"
+        kernels["block_cheb"] = kernel_entry(pff.PF_KTIME_BLOCK_CHEB, cflops, cbytes, cbound,
+                                             kernel_name(s["dim"], s["degree"], vb, split, 1, fused=True),
+                                             "block_cheb")
+    # the roofline entry is the kernel with the most time per step among the counted ones
+    counted = [k for k, v in kernels.items() if "frac" in v]
+    top = max(counted, key=lambda k: kernels[k]["s_per_step"])
+    roof = dict(kernels[top], role=roles[top])
     # the PDAS loop to convergence (Algorithm 1 repeated until A_k = A_{k-1} and ||R~|| <= 1e-10)
     # from the same iterate, in the workload's V-cycle precision
     S.set_vcycle_precision(base_prec)
@@ -473,7 +488,7 @@ def main():
         "apply_dofs_per_s_fp32": n_dofs / t_apply32,
         "stage_s_fp64": {k: r64[-1][k] for k in ("t_residual_s", "t_setup_s", "t_solve_s")},
         "roofline": roof,
-        "kernels": {"jacobian": jac, "block": blk},
+        "kernels": kernels,
         "cpu_baseline": None,
         "pdas_loop": pdas_out,
         "quantities": quant,

@@ -313,8 +313,11 @@ pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
  * enable is a combination of
  *   PF_KTIME_JACOBIAN  the Jacobian G~ (pf_jacobian_apply on the finest level, the FGMRES
  *                      operator applies, true residuals and smoother residuals), and
- *   PF_KTIME_BLOCK     the block operator B~ (the Chebyshev smoother's operator, the
- *                      eigenvalue CG, pf_block_apply on the finest level).
+ *   PF_KTIME_BLOCK     the block operator B~ (the Chebyshev smoother's operator where it
+ *                      is launched on its own, the eigenvalue CG, pf_block_apply on the
+ *                      finest level), and
+ *   PF_KTIME_BLOCK_CHEB the B~ launches that carry a fused Chebyshev step (see
+ *                      pf_set_smoother_fusion).
  * A nonzero enable clears both records and, from then on, brackets every every-th
  * such launch of each record (the 1st, (every+1)-th, ...; every in [1, 1e6]) with two
  * events on the launch stream; the Pi_C start of y is outside the bracket.  At most
@@ -323,14 +326,34 @@ pf_status pf_autotune(pf_ctx* ctx, int reps, void* stream);
  * enable = 0 stops recording and keeps the records (every is then ignored). */
 #define PF_KTIME_JACOBIAN 1
 #define PF_KTIME_BLOCK 2
+#define PF_KTIME_BLOCK_CHEB 4
 pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable, int every);
-/* One record (op = PF_KTIME_JACOBIAN or PF_KTIME_BLOCK): the launches seen since it was
+/* One record (op = PF_KTIME_JACOBIAN, PF_KTIME_BLOCK or PF_KTIME_BLOCK_CHEB): the launches seen since it was
  * cleared (bracketed or not), the number bracketed and their mean / min / max duration
  * in seconds (waits for the last bracketed launch).  count = 0 gives zero durations. */
 pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* count, double* avg_s,
                                   double* min_s, double* max_s);
 /* pf_get_kernel_timing_op with op = PF_KTIME_JACOBIAN. */
 pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s);
+/* Chebyshev smoother steps (Sec. 3.2.1) after the first one fused into the block-operator
+ * apply on levels whose B~ runs as 3D Q1 marching tiles (autotuner variants 0 / 1), which
+ * write every node exactly once: the step's vector update (residual, direction, iterate)
+ * happens where the tile writes the node, and the separate vector pass disappears.  The
+ * arithmetic per entry is the same as the separate pass's.
+ *   PF_FUSE_OFF     never;
+ *   PF_FUSE_TUNED   (default) on the levels and precisions where pf_autotune measured the
+ *                   fused step faster than apply + vector pass by more than 3%, or where
+ *                   pf_set_level_fusion chose it (untuned levels: not fused);
+ *   PF_FUSE_ALWAYS  on every marching-tile level.
+ * Drops captured V-cycle graphs.  Other shapes and levels are not affected. */
+#define PF_FUSE_OFF 0
+#define PF_FUSE_TUNED 1
+#define PF_FUSE_ALWAYS 2
+pf_status pf_set_smoother_fusion(pf_ctx* ctx, int mode);
+/* The PF_FUSE_TUNED choice of one level and precision (fused = 0 or 1), as pf_autotune
+ * would set it; used to restore cached tuning.  pf_tuning_report gives the autotuner's
+ * choice ("fused") and its two step times ("step_us": unfused, fused) per block entry. */
+pf_status pf_set_level_fusion(pf_ctx* ctx, int level, int prec, int fused);
 /* Read / force the choice of one (level, prec, mode); variant -1 = size heuristic,
  * zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */
 pf_status pf_get_tuning(pf_ctx* ctx, int level, int prec, int mode, int* variant, int* zc);

@@ -52,11 +52,14 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
 
 // one wavefront per tile; tiles ordered z-chunk fastest, then x, then y (ntx x nty tiles of
 // TX x TY cells, nzc chunks), launched as a 1D grid of ntx * nty * nzc workgroups
-template <typename T, int MODE, int TX, int TY>
+// CHEB (block operator only): instead of y, apply the Chebyshev step cf at every owned node.
+template <typename T, int MODE, int TX, int TY, bool CHEB = false>
 __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, int nzc, const T* __restrict__ x,
                                               const T* __restrict__ U, const T* __restrict__ phit,
-                                              const uint8_t* __restrict__ mask, T* __restrict__ y) {
+                                              const uint8_t* __restrict__ mask, T* __restrict__ y,
+                                              ChebFuse<T> cf = ChebFuse<T>{}) {
   static_assert(TX * TY == 64, "one wavefront per tile");
+  static_assert(!CHEB || MODE == MODE_BLOCK, "the fused Chebyshev step follows the block operator");
   constexpr bool COUPLE = (MODE == MODE_APPLY);
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
   const int bz = (int)(t % nzc);
@@ -141,7 +144,20 @@ __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, in
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int64_t o = c * nn + go;
-        y[o] = (m & mask_bit(c, 3)) ? x[o] : val[c];
+        const bool con = m & mask_bit(c, 3);
+        if constexpr (CHEB) {
+          const T c1 = c == 3 ? cf.c1p : cf.c1u, c2 = c == 3 ? cf.c2p : cf.c2u;
+          const T d = x[o];
+          const T r = cf.res[o] - (con ? d : val[c]);
+          cf.res[o] = r;
+          const T dn = c1 * d + c2 * r / cf.diag[o];
+          const T xn = cf.x[o] + dn;
+          cf.x[o] = xn;
+          if (cf.d_out) cf.d_out[o] = dn;
+          if (cf.t_next) cf.t_next[o] = con ? (cf.next_of_x ? xn : dn) : T(0);
+        } else {
+          y[o] = con ? x[o] : val[c];
+        }
       }
     }
 #pragma unroll
@@ -803,6 +819,40 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
+
+bool q1_block_cheb_fusable(const Geom& g, const CellParams& cp) {
+  if (g.d != 3 || g.p != 1 || cp.split || !cp.qcb) return false;
+  const int v = q1_variant(g, MODE_BLOCK, cp.variant);
+  return v == 0 || v == 1;
+}
+
+template <typename T>
+pf_status launch_q1_block_cheb(const Geom& g, const CellParams& cp, const T* d, const T* U, const T* phit,
+                               const uint8_t* mask, const ChebFuse<T>& cf, hipStream_t s, bool* handled) {
+  *handled = q1_block_cheb_fusable(g, cp);
+  if (!*handled || g.n_cells == 0) return PF_OK;
+  const int tile = q1_variant(g, MODE_BLOCK, cp.variant);
+  const int tx = tile == 1 ? 16 : 8;
+  const int64_t ntx = (g.nn[0] + tx - 2) / (tx - 1), nty = (g.nn[1] + 64 / tx - 2) / (64 / tx - 1);
+  const int zc = q1_chunk(g, tile, cp.zc);
+  const int nzc = (g.nn[2] + zc - 1) / zc;
+  const int64_t nb = ntx * nty * nzc;
+  if (nb > 0x7fffffff) {
+    set_error("Q1 marching tiles: too many tiles for one launch");
+    return PF_ERR_UNSUPPORTED;
+  }
+  if (tile == 1)
+    k_q1_3d<T, MODE_BLOCK, 16, 4, true><<<(unsigned)nb, 64, 0, s>>>(cp, zc, (int)ntx, nzc, d, U, phit, mask, nullptr, cf);
+  else
+    k_q1_3d<T, MODE_BLOCK, 8, 8, true><<<(unsigned)nb, 64, 0, s>>>(cp, zc, (int)ntx, nzc, d, U, phit, mask, nullptr, cf);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+template pf_status launch_q1_block_cheb<double>(const Geom&, const CellParams&, const double*, const double*,
+                                                const double*, const uint8_t*, const ChebFuse<double>&, hipStream_t,
+                                                bool*);
+template pf_status launch_q1_block_cheb<float>(const Geom&, const CellParams&, const float*, const float*, const float*,
+                                               const uint8_t*, const ChebFuse<float>&, hipStream_t, bool*);
 
 pf_status launch_cell_q1_d(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
                            const double* phit, const uint8_t* mask, double* y, hipStream_t s, bool* handled) {

@@ -107,6 +107,27 @@ pf_status launch_cell(const Geom& g, const CellParams& cp, int mode, const T* x,
 // Miehe split on Q1 levels (cell_split.hip): records of the per-point eigen-data
 // (split_record_values(d) values per cell), computed from the level's U
 int split_record_values(int d);
+// One Chebyshev step of the smoother fused into the block-operator apply (3D Q1 marching
+// tiles, which write every node once): at each node, with t = (B~ d)(node),
+//   r -= t;  d' = c1 d + c2 r / diag;  x += d';  [d_out = d'];  [t_next = Pi_C (next_of_x ? x : d')]
+// with (c1, c2) of the displacement block on u rows and of the phase-field block on phi rows.
+// d (the apply's input) is only read; d_out is a different buffer, or null.
+template <typename T>
+struct ChebFuse {
+  T* res;
+  const T* diag;
+  T* x;
+  T* d_out;
+  T* t_next;
+  T c1u, c2u, c1p, c2p;
+  int next_of_x;
+};
+// *handled = false when the level's block operator is not a 3D Q1 marching-tile shape
+template <typename T>
+pf_status launch_q1_block_cheb(const Geom& g, const CellParams& cp, const T* d, const T* U, const T* phit,
+                               const uint8_t* mask, const ChebFuse<T>& cf, hipStream_t s, bool* handled);
+bool q1_block_cheb_fusable(const Geom& g, const CellParams& cp);
+
 // Q1 block operator coefficients: values per cell, and the per-linearization pass that writes them
 int q1_block_coef_values(int d);
 pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U, double* c64, float* c32,

@@ -180,6 +180,10 @@ struct LevelBuf {
   int variant[2][2] = {{-1, -1}, {-1, -1}};
   int zc[2][2] = {{-1, -1}, {-1, -1}};
   double tune_us[2][2][16] = {};  // measured candidates (autotune report)
+  // per precision: whether the smoother's Chebyshev steps run fused into the marching-tile B~
+  // (PF_FUSE_TUNED), and the autotuner's times of one step unfused / fused (us, 0 = not timed)
+  bool fuse[2] = {false, false};
+  double fuse_us[2][2] = {};
 };
 
 struct pf_ctx {
@@ -206,11 +210,13 @@ struct pf_ctx {
   double* host_scal = nullptr;  // pinned host copy of the FGMRES scalars (kHostScal doubles)
   // optional HIP-event timing of the finest-level FP64 cell kernels (pf_set_kernel_timing):
   // record 0 = Jacobian G~, record 1 = block operator B~
+  // record 2 = B~ applies that carry a fused Chebyshev step
   int ktime_mask = 0;
-  int ktime_every = 1;            // bracket every ktime_every-th launch of a record
-  int64_t ktime_seen[2] = {0, 0};  // launches seen since the record was cleared
-  int ktime_n[2] = {0, 0};
-  std::vector<hipEvent_t> ktime_ev[2];  // pairs (start, end), kKernelTimerMax of them per record
+  int ktime_every = 1;               // bracket every ktime_every-th launch of a record
+  int64_t ktime_seen[3] = {0, 0, 0};  // launches seen since the record was cleared
+  int ktime_n[3] = {0, 0, 0};
+  std::vector<hipEvent_t> ktime_ev[3];  // pairs (start, end), kKernelTimerMax of them per record
+  int cheb_fusion = PF_FUSE_TUNED;  // Chebyshev steps fused into marching-tile B~ applies (pf_set_smoother_fusion)
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
@@ -238,7 +244,7 @@ struct pf_ctx {
     for (hipEvent_t e : aux_ev) hipEventDestroy(e);
     if (fork_ev) hipEventDestroy(fork_ev);
     if (host_scal) hipHostFree(host_scal);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 3; ++k)
       for (hipEvent_t e : ktime_ev[k]) hipEventDestroy(e);
   }
   bool has_extra = false, has_lin = false;
@@ -576,7 +582,44 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
   const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
   // the step that produces the next direction also writes t = Pi_C dv for the next apply
   const bool fuse = apply_needs_preset(c, l, prec, MODE_BLOCK);
+  // Marching tiles write every node once, so the block-operator apply of steps k >= 1 can carry
+  // the step's vector update itself; the direction then alternates between vd (odd k) and vt
+  // (even k), and the last step (odd when the degree is even) may leave Pi_C x in vt.
+  if (b.cb64 && !(b.cb_pres == c->mat.p)) PFF_TRY(refresh_block_coef(c, l, s));
+  const CellParams bcp = level_params(c, l, prec, MODE_BLOCK);
+  const bool want = c->cheb_fusion == PF_FUSE_ALWAYS || (c->cheb_fusion == PF_FUSE_TUNED && b.fuse[prec == PF_F64 ? 0 : 1]);
+  const bool fused = want && degree >= 2 && (degree % 2 == 0 || !tail_init) && q1_block_cheb_fusable(b.g, bcp);
+  const T* Ul = prec == PF_F64 ? (const T*)b.U : (const T*)b.U32;
+  const T* pl = prec == PF_F64 ? (const T*)b.phit : (const T*)b.phit32;
+  T* din = dv;
   for (int k = 0; k < degree; ++k) {
+    if (k > 0 && fused) {
+      const bool last = k + 1 == degree;
+      ChebFuse<T> cf;
+      cf.res = res;
+      cf.diag = diag;
+      cf.x = x;
+      cf.d_out = last ? nullptr : (din == dv ? t : dv);
+      cf.t_next = last && tail_init ? t : nullptr;
+      cf.c1u = (T)cu.c1[k];
+      cf.c2u = (T)cu.c2[k];
+      cf.c1p = (T)cpz.c1[k];
+      cf.c2p = (T)cpz.c2[k];
+      cf.next_of_x = 1;
+      bool handled = false;
+      const bool timed = ((c->ktime_mask >> 2) & 1) && prec == PF_F64 && l == (int)c->lev.size() - 1 &&
+                         c->ktime_seen[2]++ % c->ktime_every == 0 && c->ktime_n[2] < kKernelTimerMax;
+      hipEvent_t* ev = timed ? &c->ktime_ev[2][2 * c->ktime_n[2]++] : nullptr;
+      if (ev) PFF_HIP(hipEventRecord(ev[0], s));
+      PFF_TRY(launch_q1_block_cheb<T>(b.g, bcp, din, Ul, pl, b.mask, cf, s, &handled));
+      if (ev) PFF_HIP(hipEventRecord(ev[1], s));
+      if (!handled) {
+        set_error("fused Chebyshev step: the level's block operator is not a marching-tile shape");
+        return PF_ERR_UNSUPPORTED;
+      }
+      din = cf.d_out;
+      continue;
+    }
     if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s, fuse));
     const double c1[2] = {cu.c1[k], cpz.c1[k]}, c2[2] = {cu.c2[k], cpz.c2[k]};
     T* t_next = nullptr;
@@ -723,6 +766,10 @@ pf_status vcycle_graph(pf_ctx* c, int vprec, const double* r, double* z, hipStre
   const int k = vprec == PF_F64 ? 0 : 1;
   const int64_t n = c->lev.back().g.n_dofs;
   if (!c->vvalid[k]) {
+    // B~'s per-point coefficients follow a pressure set since the linearization here, on the
+    // caller's stream, so that the capture does not record their refresh
+    for (int l = 0; l < (int)c->lev.size(); ++l)
+      if (c->lev[l].cb64 && !(c->lev[l].cb_pres == c->mat.p)) PFF_TRY(refresh_block_coef(c, l, s));
     if (!c->cap_stream) PFF_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     if (c->vexec[k]) hipGraphExecDestroy(c->vexec[k]);
     if (c->vgraph[k]) hipGraphDestroy(c->vgraph[k]);
@@ -1183,15 +1230,15 @@ pf_status pf_jacobian_apply(pf_ctx* ctx, int level, int prec, const void* d_x, v
 
 pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable, int every) {
   NEED_CTX();
-  if (enable < 0 || enable > (PF_KTIME_JACOBIAN | PF_KTIME_BLOCK)) {
-    set_error("enable must be 0 or a combination of PF_KTIME_JACOBIAN and PF_KTIME_BLOCK");
+  if (enable < 0 || enable > (PF_KTIME_JACOBIAN | PF_KTIME_BLOCK | PF_KTIME_BLOCK_CHEB)) {
+    set_error("enable must be 0 or a combination of PF_KTIME_JACOBIAN, PF_KTIME_BLOCK and PF_KTIME_BLOCK_CHEB");
     return PF_ERR_INVALID_ARG;
   }
   if (every < 1 || every > 1000000) {
     set_error("every must be in [1, 1000000]");
     return PF_ERR_INVALID_ARG;
   }
-  for (int k = 0; k < 2 && enable; ++k)
+  for (int k = 0; k < 3 && enable; ++k)
     if (((enable >> k) & 1) && ctx->ktime_ev[k].empty()) {
       ctx->ktime_ev[k].resize(2 * kKernelTimerMax, nullptr);
       for (auto& e : ctx->ktime_ev[k]) PFF_HIP(hipEventCreate(&e));
@@ -1199,7 +1246,7 @@ pf_status pf_set_kernel_timing(pf_ctx* ctx, int enable, int every) {
   ctx->ktime_mask = enable;
   if (enable) {
     ctx->ktime_every = every;
-    for (int k = 0; k < 2; ++k) ctx->ktime_n[k] = 0, ctx->ktime_seen[k] = 0;
+    for (int k = 0; k < 3; ++k) ctx->ktime_n[k] = 0, ctx->ktime_seen[k] = 0;
   }
   return PF_OK;
 }
@@ -1211,11 +1258,11 @@ pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* c
     set_error("launches, count, avg_s, min_s and max_s must be non-NULL");
     return PF_ERR_INVALID_ARG;
   }
-  if (op != PF_KTIME_JACOBIAN && op != PF_KTIME_BLOCK) {
-    set_error("op must be PF_KTIME_JACOBIAN or PF_KTIME_BLOCK");
+  if (op != PF_KTIME_JACOBIAN && op != PF_KTIME_BLOCK && op != PF_KTIME_BLOCK_CHEB) {
+    set_error("op must be PF_KTIME_JACOBIAN, PF_KTIME_BLOCK or PF_KTIME_BLOCK_CHEB");
     return PF_ERR_INVALID_ARG;
   }
-  const int k = op == PF_KTIME_JACOBIAN ? 0 : 1;
+  const int k = op == PF_KTIME_JACOBIAN ? 0 : (op == PF_KTIME_BLOCK ? 1 : 2);
   double sum = 0.0, lo = 0.0, hi = 0.0;
   for (int i = 0; i < ctx->ktime_n[k]; ++i) {
     PFF_HIP(hipEventSynchronize(ctx->ktime_ev[k][2 * i + 1]));
@@ -1231,6 +1278,29 @@ pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* c
   *avg_s = ctx->ktime_n[k] ? sum / ctx->ktime_n[k] : 0.0;
   *min_s = lo;
   *max_s = hi;
+  return PF_OK;
+}
+
+pf_status pf_set_smoother_fusion(pf_ctx* ctx, int mode) {
+  NEED_CTX();
+  if (mode != PF_FUSE_OFF && mode != PF_FUSE_TUNED && mode != PF_FUSE_ALWAYS) {
+    set_error("mode must be PF_FUSE_OFF, PF_FUSE_TUNED or PF_FUSE_ALWAYS");
+    return PF_ERR_INVALID_ARG;
+  }
+  ctx->cheb_fusion = mode;
+  ctx->drop_graphs();
+  return PF_OK;
+}
+
+pf_status pf_set_level_fusion(pf_ctx* ctx, int level, int prec, int fused) {
+  NEED_CTX();
+  NEED_LEVEL(level);
+  if ((prec != PF_F64 && prec != PF_F32) || (fused != 0 && fused != 1)) {
+    set_error("prec must be PF_F64 or PF_F32 and fused 0 or 1");
+    return PF_ERR_INVALID_ARG;
+  }
+  ctx->lev[level].fuse[prec == PF_F64 ? 0 : 1] = fused != 0;
+  ctx->drop_graphs();
   return PF_OK;
 }
 
@@ -1604,6 +1674,60 @@ static const int kNCand = 15;
 static_assert(kNCand <= 16, "tune_us holds 16 candidates");
 static const double kTuneTie = 0.03;
 
+extern "C++" {
+// One Chebyshev smoother step of level l in precision prec, fused into the marching-tile B~ apply or
+// as the apply followed by the vector pass, timed over reps launches (us per step).  Works on the
+// level's V-cycle scratch vectors with bounded coefficients.
+template <typename T>
+static pf_status time_cheb_step(pf_ctx* c, int l, int prec, bool fused, int reps, hipEvent_t e0, hipEvent_t e1,
+                                hipStream_t s, double* us) {
+  LevelBuf& b = c->lev[l];
+  const int64_t nd = b.g.n_dofs;
+  T* d = (T*)b.vd;
+  T* t = (T*)b.vt;
+  T* res = (T*)b.vr;
+  T* x = (T*)b.vx;
+  T* dout = (T*)b.vb;
+  const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
+  const T* Ul = prec == PF_F64 ? (const T*)b.U : (const T*)b.U32;
+  const T* pl = prec == PF_F64 ? (const T*)b.phit : (const T*)b.phit32;
+  const CellParams bcp = level_params(c, l, prec, MODE_BLOCK);
+  const double c1[2] = {0.5, 0.5}, c2[2] = {1e-3, 1e-3};
+  for (T* v : {d, res, x, dout}) PFF_TRY(vec_fill<T>(v, T(1), nd, s));
+  auto step = [&]() -> pf_status {
+    if (fused) {
+      ChebFuse<T> cf;
+      cf.res = res;
+      cf.diag = diag;
+      cf.x = x;
+      cf.d_out = dout;
+      cf.t_next = nullptr;
+      cf.c1u = cf.c1p = T(c1[0]);
+      cf.c2u = cf.c2p = T(c2[0]);
+      cf.next_of_x = 0;
+      bool handled = false;
+      PFF_TRY(launch_q1_block_cheb<T>(b.g, bcp, d, Ul, pl, b.mask, cf, s, &handled));
+      if (!handled) {
+        set_error("fused Chebyshev step: not a marching-tile level");
+        return PF_ERR_UNSUPPORTED;
+      }
+      return PF_OK;
+    }
+    PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, d, t, s));
+    return vec_cheb_step<T>(res, t, d, x, diag, c1, c2, 0, b.g.n_nodes, b.g.d, b.mask, nullptr, 0, nullptr, s);
+  };
+  for (int w = 0; w < 2; ++w) PFF_TRY(step());
+  PFF_HIP(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; ++r) PFF_TRY(step());
+  PFF_HIP(hipEventRecord(e1, s));
+  PFF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  PFF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  *us = 1e3 * ms / reps;
+  return PF_OK;
+}
+}  // extern "C++"
+
 static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   if (b.g.p != 1) return PF_OK;
@@ -1659,6 +1783,18 @@ static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
       }
       b.variant[pi][mi] = bv;
       b.zc[pi][mi] = bz;
+      if (mi == 1 && st == PF_OK) {
+        // with B~ on marching tiles, time one smoother step fused and unfused; fuse only when
+        // that is clearly faster (the fused vector update is not a coalesced stream)
+        b.fuse[pi] = false;
+        b.fuse_us[pi][0] = b.fuse_us[pi][1] = 0.0;
+        if (q1_block_cheb_fusable(b.g, level_params(c, l, prec, MODE_BLOCK))) {
+          for (int f = 0; f < 2 && st == PF_OK; ++f)
+            st = prec == PF_F64 ? time_cheb_step<double>(c, l, prec, f == 1, reps, e0, e1, s, &b.fuse_us[pi][f])
+                                : time_cheb_step<float>(c, l, prec, f == 1, reps, e0, e1, s, &b.fuse_us[pi][f]);
+          if (st == PF_OK) b.fuse[pi] = b.fuse_us[pi][1] < b.fuse_us[pi][0] * (1.0 - kTuneTie);
+        }
+      }
     }
   }
   hipEventDestroy(e0);
@@ -1731,8 +1867,14 @@ pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len) {
       for (int mi = 0; mi < 2; ++mi) {
         if (pi || mi) o += ", ";
         o += "{\"prec\": \"" + std::string(pi ? "f32" : "f64") + "\", \"mode\": \"" + (mi ? "block" : "jacobian") +
-             "\", \"variant\": " + std::to_string(b.variant[pi][mi]) + ", \"zc\": " + std::to_string(b.zc[pi][mi]) +
-             ", \"us\": [";
+             "\", \"variant\": " + std::to_string(b.variant[pi][mi]) + ", \"zc\": " + std::to_string(b.zc[pi][mi]);
+        if (mi) {
+          char tmp[96];
+          snprintf(tmp, sizeof(tmp), ", \"fused\": %d, \"step_us\": [%.3f, %.3f]", b.fuse[pi] ? 1 : 0,
+                   b.fuse_us[pi][0], b.fuse_us[pi][1]);
+          o += tmp;
+        }
+        o += ", \"us\": [";
         for (int k = 0; k < kNCand; ++k) {
           if (k) o += ", ";
           char tmp[64];

@@ -22,7 +22,8 @@ PF_F64, PF_F32 = 0, 1
 PF_PREC_FULL, PF_PREC_DIAG = 0, 1
 PF_SPLIT_NONE, PF_SPLIT_MIEHE = 0, 1
 PF_COARSE_AUTO, PF_COARSE_FUSED, PF_COARSE_STEPS = 0, 1, 2
-PF_KTIME_JACOBIAN, PF_KTIME_BLOCK = 1, 2
+PF_KTIME_JACOBIAN, PF_KTIME_BLOCK, PF_KTIME_BLOCK_CHEB = 1, 2, 4
+PF_FUSE_OFF, PF_FUSE_TUNED, PF_FUSE_ALWAYS = 0, 1, 2
 PF_BOX, PF_LSHAPE = 0, 1
 PF_MASK_PHI = 8
 
@@ -100,6 +101,8 @@ SIGNATURES = {
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_tuning_report": (I, [VP, C.c_char_p, C.c_size_t]),
     "pf_set_kernel_timing": (I, [VP, I, I]),
+    "pf_set_smoother_fusion": (I, [VP, I]),
+    "pf_set_level_fusion": (I, [VP, I, I, I]),
     "pf_pdas_solve": (I, [VP, VP, VP, VP, I, D, C.POINTER(PdasReport), VP]),
     "pf_extrapolate": (I, [VP, VP, VP, D, VP, VP]),
     "pf_set_pressure": (I, [VP, D]),
@@ -499,6 +502,11 @@ class Solver:
         """PF_COARSE_AUTO (dense matrix of the coarse solve when small), PF_COARSE_FUSED or PF_COARSE_STEPS."""
         _check(lib().pf_set_coarse_mode(self.ctx, mode), "pf_set_coarse_mode")
 
+    def set_smoother_fusion(self, mode):
+        """PF_FUSE_OFF, PF_FUSE_TUNED (default) or PF_FUSE_ALWAYS: Chebyshev steps fused into
+        marching-tile block-operator applies (see pff.h)."""
+        _check(lib().pf_set_smoother_fusion(self.ctx, int(mode)), "pf_set_smoother_fusion")
+
     def set_kernel_timing(self, enable, every=1):
         """Bracket the finest-level FP64 cell kernels with HIP events (see pff.h): True or
         PF_KTIME_JACOBIAN for G~, PF_KTIME_BLOCK for B~, or both OR-ed; False stops.
@@ -536,6 +544,9 @@ class Solver:
         if key in cache:
             for ch in cache[key]:
                 pf_set_tuning(self.ctx, ch["level"], ch["prec"], ch["mode"], ch["variant"], ch["zc"])
+                if ch["mode"] == 1:
+                    _check(lib().pf_set_level_fusion(self.ctx, ch["level"], ch["prec"], int(ch.get("fused", 0))),
+                           "pf_set_level_fusion")
             return pf_tuning_report(self.ctx)
         pf_autotune(self.ctx, reps, _stream())
         rep = pf_tuning_report(self.ctx)
@@ -545,7 +556,7 @@ class Solver:
                 for ch in lv["choices"]:
                     choices.append(dict(level=lv["level"], prec=PF_F64 if ch["prec"] == "f64" else PF_F32,
                                         mode=0 if ch["mode"] == "jacobian" else 1, variant=ch["variant"],
-                                        zc=ch["zc"]))
+                                        zc=ch["zc"], fused=ch.get("fused", 0)))
             cache[key] = choices
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
             with open(cache_path, "w") as f:
