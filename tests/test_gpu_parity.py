@@ -146,12 +146,19 @@ def test_autotune_report_and_cache(tmp_path):
             assert ch["variant"] in (0, 1, 2, 3, 4)
             times = [t for v, z, t in ch["us"] if t > 0]
             assert len(times) >= 4 and min(times) > 0
+            if ch["mode"] == "block":
+                # the fused-smoother choice is timed exactly on the marching-tile levels
+                assert ch["fused"] in (0, 1)
+                tiled = ch["variant"] in (0, 1)
+                assert (min(ch["step_us"]) > 0) == tiled
+                assert ch["fused"] == 0 or ch["step_us"][1] < ch["step_us"][0]
     # cached choices are restored without timing
     S2 = gpu_solver(s)
     S2.set_linearization(dev(U), dev(phit), dev(act))
     rep2 = S2.autotune(reps=3, cache_path=str(tmp_path / "tune.json"))
     for a, b in zip(rep["levels"], rep2["levels"]):
         assert [c["variant"] for c in a["choices"]] == [c["variant"] for c in b["choices"]]
+        assert [c.get("fused") for c in a["choices"]] == [c.get("fused") for c in b["choices"]]
     x = np.random.default_rng(5).uniform(-1, 1, H.fine.n_dofs)
     assert rel_err(host(S2.jacobian_apply(-1, dev(x))), H.mg[-1].G @ x) <= 1e-12
 
