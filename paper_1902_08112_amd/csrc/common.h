@@ -199,7 +199,8 @@ pf_status nrm2_dev(const double* x, int64_t n, double* d_partials, double* d_out
 // count of non-finite entries (host)
 pf_status count_nonfinite(const double* x, int64_t n, double* d_partials, double* h_out, hipStream_t s);
 // SplitMix64 start vector of the eigenvalue estimate (block-local counters), masked
-pf_status eig_start_vector(double* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_phi,
+template <typename T>
+pf_status eig_start_vector(T* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_phi,
                            hipStream_t s);
 // y_i = x_i * dinv_i where dinv = 1/diag (constrained rows: 0)
 pf_status vec_jacobi(double* y, const double* x, const double* diag, const uint8_t* mask, int64_t nn, int d,
@@ -218,13 +219,17 @@ struct EigDev {
   double al[2][kEigMaxSteps], be[2][kEigMaxSteps];
 };
 // z = p = D^-1 r (masked), then rz = rz0 = (r, z) per block
-pf_status eig_cg_begin(const double* r, double* z, double* p, const double* diag, const uint8_t* mask, int64_t nn,
+// (T = double or float vectors; the dots accumulate in FP64, the coefficients are FP64)
+template <typename T>
+pf_status eig_cg_begin(const T* r, T* z, T* p, const T* diag, const uint8_t* mask, int64_t nn,
                        int d, double* d_partials, EigDev* st, hipStream_t s);
 // alpha_b = rz_b / (p, Ap)_b (a block with (p, Ap)_b <= 0 stops)
-pf_status eig_cg_alpha(const double* p, const double* Ap, int64_t nn, int d, double* d_partials, EigDev* st,
+template <typename T>
+pf_status eig_cg_alpha(const T* p, const T* Ap, int64_t nn, int d, double* d_partials, EigDev* st,
                        hipStream_t s);
 // r -= alpha Ap, z = D^-1 r, beta_b = (r, z)_b / rz_b, p = z + beta p; a block stops once rz_b <= 1e-24 rz0_b
-pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const double* diag, const uint8_t* mask,
+template <typename T>
+pf_status eig_cg_beta(T* r, const T* Ap, T* z, T* p, const T* diag, const uint8_t* mask,
                       int64_t nn, int d, double* d_partials, EigDev* st, hipStream_t s);
 
 // ---------------------------------------------------------------------------

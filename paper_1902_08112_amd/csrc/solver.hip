@@ -803,25 +803,35 @@ pf_status vcycle_any(pf_ctx* c, int vprec, const double* r, double* z, hipStream
 // ---------------------------------------------------------------------------
 // Launch the Jacobi-PCG of level l (both diagonal blocks, lockstep); the
 // coefficients stay in c->eigdev[l] until eig_from_cg reads them.
-pf_status launch_eig_cg(pf_ctx* c, int l, double* part, hipStream_t s) {
+template <typename T>
+static pf_status eig_cg_run(pf_ctx* c, int l, int prec, double* part, hipStream_t s) {
   LevelBuf& b = c->lev[l];
   const Geom& g = b.g;
-  double* r = (double*)b.vr;
-  double* z = (double*)b.vd;
-  double* p = (double*)b.vb;
-  double* Ap = (double*)b.vt;
+  T* r = (T*)b.vr;
+  T* z = (T*)b.vd;
+  T* p = (T*)b.vb;
+  T* Ap = (T*)b.vt;
+  const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
   EigDev* st = c->eigdev + l;
   const uint64_t seed = c->opt.eig_seed;
   const uint64_t su = seed + (uint64_t)l * 0x1000003ull + 0ull * 0x10001ull;
   const uint64_t sp = seed + (uint64_t)l * 0x1000003ull + 1ull * 0x10001ull;
-  PFF_TRY(eig_start_vector(r, b.mask, g.n_nodes, g.d, su, sp, s));
-  PFF_TRY(eig_cg_begin(r, z, p, b.diag, b.mask, g.n_nodes, g.d, part, st, s));
+  PFF_TRY(eig_start_vector<T>(r, b.mask, g.n_nodes, g.d, su, sp, s));
+  PFF_TRY(eig_cg_begin<T>(r, z, p, diag, b.mask, g.n_nodes, g.d, part, st, s));
   for (int it = 0; it < c->opt.eig_cg_steps; ++it) {
-    PFF_TRY(level_apply(c, l, PF_F64, MODE_BLOCK, p, Ap, s));
-    PFF_TRY(eig_cg_alpha(p, Ap, g.n_nodes, g.d, part, st, s));
-    PFF_TRY(eig_cg_beta(r, Ap, z, p, b.diag, b.mask, g.n_nodes, g.d, part, st, s));
+    PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, p, Ap, s));
+    PFF_TRY(eig_cg_alpha<T>(p, Ap, g.n_nodes, g.d, part, st, s));
+    PFF_TRY(eig_cg_beta<T>(r, Ap, z, p, diag, b.mask, g.n_nodes, g.d, part, st, s));
   }
   return PF_OK;
+}
+
+// The eigenvalue CG of a level runs in the precision the V-cycle applies that level's operator
+// in: FP64 for FP64 V-cycles and the coarsest level, FP32 on the other levels of FP32 V-cycles
+// (the bounds only place the Chebyshev interval, which carries a 1.2 safety factor).
+pf_status launch_eig_cg(pf_ctx* c, int l, double* part, hipStream_t s) {
+  const int prec = level_prec(c, l, c->vprec);
+  return prec == PF_F64 ? eig_cg_run<double>(c, l, prec, part, s) : eig_cg_run<float>(c, l, prec, part, s);
 }
 
 // Lanczos tridiagonal of the CG coefficients -> extreme eigenvalues per block

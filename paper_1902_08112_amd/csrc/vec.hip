@@ -166,13 +166,14 @@ __device__ inline double block_sum(double v) {
 }
 
 // partials[k * gridDim.x + block] for segment k = [b_k, b_{k+1}), k < nseg <= 2
-__global__ void k_dot_segments(const double* x, const double* y, int64_t b0, int64_t b1, int64_t b2, int nseg,
+template <typename T>
+__global__ void k_dot_segments(const T* x, const T* y, int64_t b0, int64_t b1, int64_t b2, int nseg,
                                double* partials) {
   for (int k = 0; k < nseg; ++k) {
     const int64_t lo = k == 0 ? b0 : b1, hi = k == 0 ? b1 : b2;
     double acc = 0.0;
     for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += (int64_t)gridDim.x * blockDim.x)
-      acc += x[i] * y[i];
+      acc += (double)x[i] * (double)y[i];
     const double b = block_sum(acc);
     if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = b;
   }
@@ -192,7 +193,7 @@ static pf_status dot_segments(const double* x, const double* y, const int64_t bo
                               double* d_out, hipStream_t s) {
   const int64_t n = bounds[nseg];
   int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
-  k_dot_segments<<<nb, kRedBlock, 0, s>>>(x, y, bounds[0], bounds[1], bounds[2], nseg, d_part);
+  k_dot_segments<double><<<nb, kRedBlock, 0, s>>>(x, y, bounds[0], bounds[1], bounds[2], nseg, d_part);
   PFF_CHECK_LAUNCH();
   k_finalize<<<1, kRedBlock, 0, s>>>(d_part, nb, nseg, d_out);
   PFF_CHECK_LAUNCH();
@@ -306,7 +307,8 @@ __device__ inline uint64_t sm64_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_eig_start(double* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_p) {
+template <typename T>
+__global__ void k_eig_start(T* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_p) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int64_t nu = (int64_t)d * nn;
   GRID_STRIDE(i, n) {
@@ -316,12 +318,13 @@ __global__ void k_eig_start(double* v, const uint8_t* mask, int64_t nn, int d, u
     const uint64_t ctr = (uint64_t)(phi ? i - nu : i);
     const uint64_t z = sm64_mix((phi ? seed_p : seed_u) + (ctr + 1ull) * 0x9E3779B97F4A7C15ull);
     const double u = (double)(z >> 11) * 0x1.0p-53;
-    v[i] = (mask[node] & mask_bit(c, d)) ? 0.0 : 2.0 * u - 1.0;
+    v[i] = (T)((mask[node] & mask_bit(c, d)) ? 0.0 : 2.0 * u - 1.0);
   }
 }
-pf_status eig_start_vector(double* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_phi,
+template <typename T>
+pf_status eig_start_vector(T* v, const uint8_t* mask, int64_t nn, int d, uint64_t seed_u, uint64_t seed_phi,
                            hipStream_t s) {
-  k_eig_start<<<nblocks((d + 1) * nn), 256, 0, s>>>(v, mask, nn, d, seed_u, seed_phi);
+  k_eig_start<T><<<nblocks((d + 1) * nn), 256, 0, s>>>(v, mask, nn, d, seed_u, seed_phi);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
@@ -368,25 +371,26 @@ pf_status vec_axpy_blocks(double* y, const double* x, const double alpha[2], int
 // ---------------------------------------------------------------------------
 // z = D^-1 (r - alpha q) on free DoFs (r updated when q != nullptr), p = z if
 // p != nullptr; partials of (r, z) per block
-__global__ void k_eig_precond(double* r, const double* q, const EigDev* st, double* z, double* p, const double* diag,
+template <typename T>
+__global__ void k_eig_precond(T* r, const T* q, const EigDev* st, T* z, T* p, const T* diag,
                               const uint8_t* mask, int64_t nn, int d, double* partials) {
   const int64_t nu = (int64_t)d * nn, n = nu + nn;
   for (int k = 0; k < 2; ++k) {
     const int64_t lo = k == 0 ? 0 : nu, hi = k == 0 ? nu : n;
-    const double na = q ? -st->alpha[k] : 0.0;
+    const T na = q ? T(-st->alpha[k]) : T(0);
     double acc = 0.0;
     for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
          i += (int64_t)gridDim.x * blockDim.x) {
-      double ri = r[i];
+      T ri = r[i];
       if (q) {
         ri += na * q[i];
         r[i] = ri;
       }
       const int c = (int)(i / nn);
-      const double zi = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? 0.0 : ri / diag[i];
+      const T zi = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? T(0) : ri / diag[i];
       z[i] = zi;
       if (p) p[i] = zi;
-      acc += ri * zi;
+      acc += (double)ri * (double)zi;
     }
     const double b = block_sum(acc);
     if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = b;
@@ -432,42 +436,46 @@ __global__ void k_eig_update(const double* partials, int nparts, EigDev* st, int
   }
 }
 
-__global__ void k_eig_xpby(double* p, const double* z, const EigDev* st, int64_t nu, int64_t n) {
-  const double bu = st->beta[0], bp = st->beta[1];
+template <typename T>
+__global__ void k_eig_xpby(T* p, const T* z, const EigDev* st, int64_t nu, int64_t n) {
+  const T bu = T(st->beta[0]), bp = T(st->beta[1]);
   GRID_STRIDE(i, n) p[i] = z[i] + (i >= nu ? bp : bu) * p[i];
 }
 
-pf_status eig_cg_begin(const double* r, double* z, double* p, const double* diag, const uint8_t* mask, int64_t nn,
+template <typename T>
+pf_status eig_cg_begin(const T* r, T* z, T* p, const T* diag, const uint8_t* mask, int64_t nn,
                        int d, double* d_part, EigDev* st, hipStream_t s) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
-  k_eig_precond<<<nb, kRedBlock, 0, s>>>(const_cast<double*>(r), nullptr, st, z, p, diag, mask, nn, d, d_part);
+  k_eig_precond<T><<<nb, kRedBlock, 0, s>>>(const_cast<T*>(r), nullptr, st, z, p, diag, mask, nn, d, d_part);
   PFF_CHECK_LAUNCH();
   k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 0);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
 
-pf_status eig_cg_alpha(const double* p, const double* Ap, int64_t nn, int d, double* d_part, EigDev* st,
+template <typename T>
+pf_status eig_cg_alpha(const T* p, const T* Ap, int64_t nn, int d, double* d_part, EigDev* st,
                        hipStream_t s) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
-  k_dot_segments<<<nb, kRedBlock, 0, s>>>(p, Ap, 0, (int64_t)d * nn, n, 2, d_part);
+  k_dot_segments<T><<<nb, kRedBlock, 0, s>>>(p, Ap, 0, (int64_t)d * nn, n, 2, d_part);
   PFF_CHECK_LAUNCH();
   k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 1);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
 
-pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const double* diag, const uint8_t* mask,
+template <typename T>
+pf_status eig_cg_beta(T* r, const T* Ap, T* z, T* p, const T* diag, const uint8_t* mask,
                       int64_t nn, int d, double* d_part, EigDev* st, hipStream_t s) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
-  k_eig_precond<<<nb, kRedBlock, 0, s>>>(r, Ap, st, z, nullptr, diag, mask, nn, d, d_part);
+  k_eig_precond<T><<<nb, kRedBlock, 0, s>>>(r, Ap, st, z, nullptr, diag, mask, nn, d, d_part);
   PFF_CHECK_LAUNCH();
   k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 2);
   PFF_CHECK_LAUNCH();
-  k_eig_xpby<<<nblocks(n), 256, 0, s>>>(p, z, st, (int64_t)d * nn, n);
+  k_eig_xpby<T><<<nblocks(n), 256, 0, s>>>(p, z, st, (int64_t)d * nn, n);
   PFF_CHECK_LAUNCH();
   return PF_OK;
 }
@@ -484,6 +492,15 @@ pf_status eig_cg_beta(double* r, const double* Ap, double* z, double* p, const d
                                       int, const uint8_t*, T*, int, const T*, hipStream_t);
 INST_T(double)
 INST_T(float)
+#define INST_EIG(T)                                                                                            \
+  template pf_status eig_start_vector<T>(T*, const uint8_t*, int64_t, int, uint64_t, uint64_t, hipStream_t);   \
+  template pf_status eig_cg_begin<T>(const T*, T*, T*, const T*, const uint8_t*, int64_t, int, double*, EigDev*, \
+                                     hipStream_t);                                                              \
+  template pf_status eig_cg_alpha<T>(const T*, const T*, int64_t, int, double*, EigDev*, hipStream_t);          \
+  template pf_status eig_cg_beta<T>(T*, const T*, T*, T*, const T*, const uint8_t*, int64_t, int, double*,      \
+                                    EigDev*, hipStream_t);
+INST_EIG(double)
+INST_EIG(float)
 template pf_status vec_cast<double, float>(float*, const double*, int64_t, hipStream_t);
 template pf_status vec_cast<float, double>(double*, const float*, int64_t, hipStream_t);
 

@@ -89,8 +89,11 @@ def test_batch_newton_matches_single_instances(dim, prec):
         assert abs(reps[b]["gmres_iters"] - rep.gmres_iters) <= 1
         assert reps[b]["n_active"] == rep.n_active
         assert e <= 1e-6
+        # the batched eigenvalue CG runs in FP64 on every level; the single-instance one in the
+        # V-cycle's precision (FP32 on the levels above the coarsest with FP32 V-cycles)
         for l in range(BS.L):
-            assert np.allclose(eig_b[b][l], S.eig_bounds(l), rtol=1e-8)
+            tol = 1e-8 if (prec == "f64" or l == 0) else 1e-4
+            assert np.allclose(eig_b[b][l], S.eig_bounds(l), rtol=tol)
 
 
 def test_batch_vcycle_linear_and_masked():
