@@ -5,7 +5,8 @@
 * anisotropic non-cubic meshes with non-unit aspect ratio, whose marching tiles, bricks and
   chunks are ragged in every direction;
 * a phase field that is active on every node (every phi row is an identity row);
-* the degenerate material kappa = 0 (no residual stiffness: g(0) = 0) with p = 0.
+* the degenerate material kappa = 0 (no residual stiffness: g(0) = 0) with p = 0;
+* the Chebyshev steps fused into marching-tile block applies on ragged tiles and chunks.
 Same bars as the main parity tests: FP64 operators 1e-12, FP32 2e-6, V-cycles 1e-11, Newton
 updates 1e-5 (both solves at 1e-8).
 """
@@ -128,6 +129,20 @@ def test_anisotropic_ragged_meshes(name):
     check_operators(s, H, S, variants if s["degree"] == 1 else [(None, None)])
     check_vcycle(s, U, phit, act, H, S)
     check_newton(s)
+
+
+@pytest.mark.parametrize("name", ["aniso_3d", "one_level_3d"])
+def test_fused_smoother_on_ragged_tiles(name):
+    """The Chebyshev steps fused into marching-tile B~ applies on meshes whose tiles and chunks
+    are ragged (and on a one-level hierarchy, where the coarse solve's per-step launches use
+    them): V-cycles match the oracle in every coarse-solve path."""
+    from paper_1902_08112_amd import pff
+    s, U, phit, act, H, S = setup(name, seed=21)
+    for l in range(s["n_levels"]):
+        for prec in (pff.PF_F64, pff.PF_F32):
+            pff.pf_set_tuning(S.ctx, l, prec, 1, 1, 3)
+    S.set_smoother_fusion(pff.PF_FUSE_ALWAYS)
+    check_vcycle(s, U, phit, act, H, S)
 
 
 def test_phase_field_active_everywhere():
