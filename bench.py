@@ -15,8 +15,8 @@ and the smoother's block operator B~, with HIP events on the launch stream
 (pf_set_kernel_timing); "kernels" reports both (launches per step, mean launch
 duration, achieved = algorithmic flops or bytes per launch / mean duration),
 and the roofline entry is the one with the larger time per step among those
-with an algorithmic count (B~ is counted without the split: on Q1 levels, where it reads
-stored per-point coefficients, and on 3D Q2).  traffic = HBM bytes per launch from the
+with an algorithmic count (B~ is counted on Q1 levels, where it reads stored
+per-point coefficients or the split's eigen-records, and on 3D Q2).  traffic = HBM bytes per launch from the
 committed rocprofv3 FETCH_SIZE / WRITE_SIZE summaries of this command
 (profiles/<workload>_apply_traffic.json for G~, _block_traffic.json for B~),
 while the kernel's sources are unchanged.  After the timed region a plain
@@ -60,6 +60,10 @@ SPLIT_REC_BYTES_PER_CELL = {2: 5 * 4 * 8.0, 3: 8 * 8 * 8.0}
 BLOCK_FLOP_PER_CELL = {(2, 1): 396.0, (3, 1): 1512.0, (3, 2): 7776.0}
 BLOCK_BYTES_PER_NODE_F64 = {(2, 1): 8 * 6 + 8 + 1.0, (3, 1): 8 * 8 + 8 + 1.0, (3, 2): 8 * 8 + 1.0}
 BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 54 * 8.0}
+# B~ of the Miehe split (3D Q1) from the per-point eigen-records: the unsplit block count plus the
+# tangent's eigenbasis rotations in the displacement rows (190 flops per point; the phase-field
+# rows take E_s^+ from the eigenvalues); x, y, phi~ and the mask per node plus the 512 B record
+SPLIT_BLOCK_FLOP_PER_CELL = {3: 1512.0 + 8 * 190.0}
 # every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
 # timed FP64 steps (a bracket delays the stream by a few microseconds)
 KT_EVERY = 4
@@ -388,13 +392,17 @@ def main():
     # the block operator B~ (counted without the split, on Q1 and 3D Q2)
     vb = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 1)[0]
     key = (s["dim"], s["degree"])
-    if key in BLOCK_FLOP_PER_CELL and not split:
+    if split and s["dim"] in SPLIT_BLOCK_FLOP_PER_CELL:
+        bflops = SPLIT_BLOCK_FLOP_PER_CELL[s["dim"]] * n_cells
+        bbytes = BLOCK_BYTES_PER_NODE_F64[key] * n_nodes + SPLIT_REC_BYTES_PER_CELL[s["dim"]] * n_cells
+    elif key in BLOCK_FLOP_PER_CELL and not split:
         bflops = BLOCK_FLOP_PER_CELL[key] * n_cells
         bbytes = BLOCK_BYTES_PER_NODE_F64[key] * n_nodes + BLOCK_COEF_BYTES_PER_CELL[key] * n_cells
-        # flop/B is near the FP64 ridge (9.8): the binding roof is the larger of the two times
-        bbound = "alu" if bflops / FP64_PEAK_TFLOPS / 1e12 >= bbytes / HBM_PEAK_GBS / 1e9 else "hbm"
     else:
-        bflops = bbytes = bbound = None
+        bflops = bbytes = None
+    # flop/B is near the FP64 ridge (9.8): the binding roof is the larger of the two times
+    bbound = None if bflops is None else (
+        "alu" if bflops / FP64_PEAK_TFLOPS / 1e12 >= bbytes / HBM_PEAK_GBS / 1e9 else "hbm")
     blk = kernel_entry(pff.PF_KTIME_BLOCK, bflops, bbytes, bbound,
                        kernel_name(s["dim"], s["degree"], vb, split, 1), "block")
     kernels = {"jacobian": jac, "block": blk}
