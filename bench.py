@@ -10,7 +10,7 @@ each time from the same iterate U_k (the reset copy is inside the timed loop).
 value = fine-level DoFs per second of Newton steps in the workload's own
 V-cycle precision; the other precision's step time and the speedup are
 reported beside it.  Inside the timed FP64 Newton steps the library brackets
-every 4th launch of the two finest-level FP64 cell kernels, the Jacobian G~
+every 8th launch of the two finest-level FP64 cell kernels, the Jacobian G~
 and the smoother's block operator B~, with HIP events on the launch stream
 (pf_set_kernel_timing); "kernels" reports both (launches per step, mean launch
 duration, achieved = algorithmic flops or bytes per launch / mean duration),
@@ -66,7 +66,7 @@ BLOCK_COEF_BYTES_PER_CELL = {(2, 1): 4 * 8.0, (3, 1): 8 * 8.0, (3, 2): 54 * 8.0}
 SPLIT_BLOCK_FLOP_PER_CELL = {3: 1512.0 + 8 * 190.0}
 # every KT_EVERY-th launch of each fine-level FP64 cell kernel is bracketed with HIP events in the
 # timed FP64 steps (a bracket delays the stream by a few microseconds)
-KT_EVERY = 4
+KT_EVERY = 8
 # a Chebyshev step fused into a marching-tile B~ apply (per DoF: r -= t, d' = c1 d + c2 r / diag,
 # x += d'; bytes: r read and written, diag, x read and written, d' written)
 CHEB_FLOP_PER_DOF = 7.0
