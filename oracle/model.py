@@ -285,17 +285,6 @@ def assemble_jacobian(lev, mat, U, phit, couple=True):
     return G
 
 
-def apply_ebe(lev, mat, U, phit, x, couple=True):
-    """Element-by-element apply y = G(U) x (no assembly), for sizes where CSR is too big."""
-    tab = CellTables(lev)
-    y = np.zeros(lev.n_dofs)
-    for cells in _chunks(lev.n_cells, chunk_size(lev)):
-        K = element_jacobian(lev, tab, mat, U, phit, cells, couple)
-        ld = local_dofs(lev, cells)
-        np.add.at(y, ld, np.einsum("ckl,cl->ck", K, x[ld]))
-    return y
-
-
 def cells_touching_nodes(lev, nodes):
     """Indices of active cells that contain any of the given nodes."""
     hit = np.zeros(lev.n_nodes, dtype=bool)
