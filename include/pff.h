@@ -427,6 +427,12 @@ pf_status pf_batch_jacobian_apply(pf_batch* b, int level, int prec, const void* 
 pf_status pf_batch_vcycle(pf_batch* b, int prec, const double* d_r, double* d_z, void* stream);
 /* Raw Ritz estimates of instance inst on level l (as pf_get_eig_bounds). */
 pf_status pf_batch_get_eig_bounds(pf_batch* b, int level, int inst, double out[4]);
+/* Fix the bounds of instance inst on level l (as pf_set_eig_bounds: kept by
+ * later pf_batch_set_linearization calls until cleared with in == NULL; the
+ * device copy of the Chebyshev coefficients is rewritten at once, with a
+ * synchronous copy, when a linearization is set).  Lets the oracle and the
+ * batch run V-cycles with identical smoother intervals (Sec. 3.2.1). */
+pf_status pf_batch_set_eig_bounds(pf_batch* b, int level, int inst, const double in[4]);
 pf_status pf_batch_set_vcycle_precision(pf_batch* b, int prec);
 /* Graph replay of the batched V-cycle (default on; see pf_set_graphs).  Its
  * coefficients are read from device memory, so one capture serves every step. */

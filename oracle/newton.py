@@ -55,5 +55,5 @@ def newton_step(hier, U, U_old, phit, solver="fgmres", eig_bounds=None):
                           rtol=o.gmres_rtol, restart=o.gmres_restart, max_iter=o.gmres_max_iter,
                           atol=o.gmres_atol)
     res = float(np.linalg.norm(Rt - Gt @ dU))
-    return dict(U=U + dU, dU=dU, active=active, v=v, R=R, Rt=Rt, constrained=cons,
+    return dict(U=U + dU, dU=dU, active=active, v=v, R=R, Rt=Rt, Gt=Gt, constrained=cons,
                 n_active=int(active.sum()), rel_res=res / float(np.linalg.norm(Rt)), info=info)

@@ -434,6 +434,7 @@ struct BLevel {
   double* d_coef_s = nullptr;  // [cheb_degree][B][4]
   double* d_coef_c = nullptr;  // [coarse_degree][B][4] (level 0)
   std::vector<double> eig;     // [B][4]
+  std::vector<double> eig_fix; // [B][4]: bounds fixed by pf_batch_set_eig_bounds (0: estimate)
   int d = 0, p = 0, B = 0;
   int split = PF_SPLIT_NONE;
   BView view() const {
@@ -615,6 +616,7 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
     bl.d_coef_s = cv.take<double>((size_t)o.cheb_degree * n * 4);
     bl.d_coef_c = cv.take<double>((size_t)o.coarse_degree * n * 4);
     bl.eig.assign(4 * n, 1.0);
+    bl.eig_fix.assign(4 * n, 0.0);
   }
   const BLevel& f = lev[L - 1];
   const size_t nd = f.n_dofs, nn = f.n_nodes;
@@ -995,6 +997,9 @@ pf_status bestimate_eigs(pf_batch* c, int l, hipStream_t s) {
     bl.eig[4 * b + 2 * blk] = tri_eig(a, off, 0);
     bl.eig[4 * b + 2 * blk + 1] = tri_eig(a, off, (int)n - 1);
   }
+  for (int b = 0; b < B; ++b)
+    if (bl.eig_fix[4 * b] > 0.0)
+      for (int k = 0; k < 4; ++k) bl.eig[4 * b + k] = bl.eig_fix[4 * b + k];
   return PF_OK;
 }
 
@@ -1354,6 +1359,32 @@ pf_status pf_batch_get_eig_bounds(pf_batch* bt, int level, int inst, double out[
     return PF_ERR_INVALID_ARG;
   }
   for (int k = 0; k < 4; ++k) out[k] = bt->lev[level].eig[4 * inst + k];
+  return PF_OK;
+}
+
+pf_status pf_batch_set_eig_bounds(pf_batch* bt, int level, int inst, const double in[4]) {
+  NEED_BATCH();
+  if (level < 0 || level >= bt->L || inst < 0 || inst >= bt->B) {
+    set_error("bad level or instance");
+    return PF_ERR_INVALID_ARG;
+  }
+  BLevel& bl = bt->lev[level];
+  if (!in) {
+    for (int k = 0; k < 4; ++k) bl.eig_fix[4 * inst + k] = 0.0;
+    return PF_OK;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (!(in[k] > 0.0) || !std::isfinite(in[k])) {
+      set_error("eigenvalue bounds must be positive and finite");
+      return PF_ERR_INVALID_ARG;
+    }
+  if (in[0] > in[1] || in[2] > in[3]) {
+    set_error("need lam_min <= lam_max per block");
+    return PF_ERR_INVALID_ARG;
+  }
+  for (int k = 0; k < 4; ++k) bl.eig_fix[4 * inst + k] = bl.eig[4 * inst + k] = in[k];
+  // the Chebyshev coefficients live in device memory (captured V-cycles read them there)
+  if (bt->has_lin) PFF_TRY(upload_cheb(bt, nullptr));
   return PF_OK;
 }
 

@@ -120,6 +120,7 @@ SIGNATURES = {
     "pf_batch_jacobian_apply": (I, [VP, I, I, VP, VP, VP]),
     "pf_batch_vcycle": (I, [VP, I, VP, VP, VP]),
     "pf_batch_get_eig_bounds": (I, [VP, I, I, C.POINTER(D)]),
+    "pf_batch_set_eig_bounds": (I, [VP, I, I, C.POINTER(D)]),
     "pf_batch_set_vcycle_precision": (I, [VP, I]),
     "pf_batch_set_graphs": (I, [VP, I]),
     "pf_batch_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
@@ -664,6 +665,10 @@ class BatchSolver:
         out = (D * 4)()
         _check(lib().pf_batch_get_eig_bounds(self.b, level % self.L, inst, out), "pf_batch_get_eig_bounds")
         return list(out)
+
+    def set_eig_bounds(self, level, inst, bounds):
+        arr = None if bounds is None else (D * 4)(*[float(v) for v in bounds])
+        _check(lib().pf_batch_set_eig_bounds(self.b, level % self.L, inst, arr), "pf_batch_set_eig_bounds")
 
     def set_vcycle_precision(self, prec):
         _check(lib().pf_batch_set_vcycle_precision(self.b, prec), "pf_batch_set_vcycle_precision")

@@ -7,6 +7,22 @@ from oracle import mg, model
 EIG_DUMMY = dict(u=(0.5, 2.0), phi=(0.5, 2.0))
 
 
+def oracle_bounds(H):
+    """The oracle's own eigenvalue estimates per level: [lam_min_u, lam_max_u, lam_min_phi, lam_max_phi]."""
+    return [[m.eig["u"][0], m.eig["u"][1], m.eig["phi"][0], m.eig["phi"][1]] for m in H.mg]
+
+
+def inject_bounds(S, H):
+    """Fix the library's smoother intervals to the oracle's estimates (oracle -> library, never back)."""
+    for l, b in enumerate(oracle_bounds(H)):
+        S.set_eig_bounds(l, b)
+
+
+def inject_batch_bounds(BS, b, H):
+    for l, e in enumerate(oracle_bounds(H)):
+        BS.set_eig_bounds(l, b, e)
+
+
 def torch_mod():
     import torch
     return torch
@@ -54,3 +70,14 @@ def block_rel_errs(a, b, nn, d):
     out["u"] = rel_err(a[: d * nn], b[: d * nn])
     out["phi"] = rel_err(a[d * nn:], b[d * nn:])
     return out
+
+
+def oracle_residual_of(ref, dU):
+    """True relative residual ||R~ - G~ dU|| / ||R~|| of an update, with the oracle's own R~ and G~."""
+    return float(np.linalg.norm(ref["Rt"] - ref["Gt"] @ dU) / np.linalg.norm(ref["Rt"]))
+
+
+def tie_band(v):
+    """Nodes whose active-set decision value is at rounding level (|v| <= 1e-10 max|v|)."""
+    v = np.asarray(v)
+    return int((np.abs(v) <= 1e-10 * np.abs(v).max()).sum())

@@ -1,6 +1,12 @@
 """Batched solver (pf_batch_*): parity with the oracle and with the same instances solved one by one.
 
 Tolerances: batched FP64 applies vs oracle 1e-12 per instance and level;
+batched V-cycles vs the oracle's V-cycle with the oracle's smoother intervals
+1e-11 (FP64 levels) and 1e-4 (FP32 levels); batched Newton steps vs the
+oracle's Newton step: |dU - dU_oracle| <= 1e-5 |dU_oracle| (both solves at
+1e-8 of the same system), the oracle's own true residual of the batched
+update <= 1.1e-8, FGMRES iteration counts within 1 of the oracle's with FP64
+V-cycles, the same active-set size outside the band of rounding-level ties;
 eigenvalue estimates vs single-instance contexts 1e-8 (same SplitMix64
 streams, different reduction order); Newton steps vs single-instance steps:
 same FGMRES iteration counts (+-1) and |dU - dU_single| <= 1e-6 |dU_single|
@@ -10,7 +16,9 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import EIG_DUMMY, dev, gpu_solver, host, mask_to_dofs, oracle_hierarchy, rel_err
+from gpu_common import (EIG_DUMMY, dev, gpu_solver, host, inject_batch_bounds, mask_to_dofs, oracle_hierarchy,
+                        oracle_residual_of, rel_err, tie_band)
+from oracle import newton
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +104,75 @@ def test_batch_newton_matches_single_instances(dim, prec):
             assert np.allclose(eig_b[b][l], S.eig_bounds(l), rtol=tol)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_vcycle_matches_oracle(dim):
+    """The batched P_full V-cycle of every instance against the oracle's V-cycle (Sec. 3.3), with
+    the oracle's own eigenvalue estimates fixed in the batch; eager and graph replays."""
+    from paper_1902_08112_amd import PF_F32, PF_F64
+    specs = small_batch(dim, seed=6)
+    print(f"[case] batch vcycle vs oracle dim={dim} n={len(specs)}", flush=True)
+    BS = batch_solver(specs)
+    Us, pts, acts, Hs = [], [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 140 + b)
+        act = W.random_active(s, 150 + b, 0.1)
+        H = oracle_hierarchy(s)
+        H.set_linearization(U, phit, act)
+        Us.append(U), pts.append(phit), acts.append(act), Hs.append(H)
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    for b in range(len(specs)):
+        inject_batch_bounds(BS, b, Hs[b])
+    rs = [np.random.default_rng(160 + b).uniform(-1, 1, u.size) for b, u in enumerate(Us)]
+    z_ref = [Hs[b].vcycle(rs[b]) for b in range(len(specs))]
+    for graphs in (False, True, True):
+        BS.set_graphs(graphs)
+        zs = BS.unpack(BS.vcycle(BS.pack(rs), PF_F64))
+        zs32 = BS.unpack(BS.vcycle(BS.pack(rs), PF_F32))
+        for b in range(len(specs)):
+            e, e32 = rel_err(zs[b], z_ref[b]), rel_err(zs32[b], z_ref[b])
+            print(f"  graphs {graphs} inst {b}: rel {e:.2e} FP32 levels {e32:.2e}", flush=True)
+            assert e <= 1e-11 and e32 <= 1e-4
+
+
+def check_batch_newton_vs_oracle(specs, states, Ub, reps, insts, prec):
+    """Batched Newton updates of the given instances against the oracle's Newton step."""
+    for b in insts:
+        s = specs[b]
+        U0, Uold, phit = states[b]
+        H = oracle_hierarchy(s)
+        ref = newton.newton_step(H, U0, Uold, phit)
+        dU = Ub[b] - U0
+        e = rel_err(dU, ref["dU"])
+        band = tie_band(ref["v"])
+        nb, no = reps[b]["n_active"], ref["n_active"]
+        res = oracle_residual_of(ref, dU) if nb == no else None
+        print(f"  inst {b} ({s['n_cells'][0]}^{s['dim']}): batch its {reps[b]['gmres_iters']} |A| {nb}; oracle its "
+              f"{ref['info']['iters']} |A| {no}, tie band {band}; |dU - dU_or|/|dU_or| {e:.2e}; oracle residual of "
+              f"the batched update {'n/a (active sets differ inside the tie band)' if res is None else f'{res:.2e}'}",
+              flush=True)
+        assert reps[b]["converged"] and reps[b]["rel_residual"] <= 1e-8
+        assert abs(nb - no) <= band
+        assert e <= 1e-5
+        if res is not None:
+            assert res <= 1.1e-8
+        if prec == "f64":
+            assert abs(reps[b]["gmres_iters"] - ref["info"]["iters"]) <= 1
+
+
+@pytest.mark.parametrize("dim,prec", [(2, "f64"), (2, "f32"), (3, "f64"), (3, "f32")])
+def test_batch_newton_matches_oracle(dim, prec):
+    from paper_1902_08112_amd import pff
+    specs = small_batch(dim, seed=2)
+    for s in specs:
+        s["vcycle"] = prec
+    print(f"[case] batch newton vs oracle dim={dim} {prec} n={len(specs)}", flush=True)
+    states = [W.make_state(s) for s in specs]
+    BS = batch_solver(specs, vcycle_precision=pff.PF_F32 if prec == "f32" else pff.PF_F64)
+    U = BS.pack([st[0] for st in states])
+    _, reps = BS.newton_step(U, BS.pack([st[1] for st in states]), BS.pack([st[2] for st in states], nodes=True))
+    check_batch_newton_vs_oracle(specs, states, BS.unpack(U), reps, range(len(specs)), prec)
+
+
 def test_batch_vcycle_linear_and_masked():
     specs = small_batch(2, seed=3)
     BS = batch_solver(specs)
@@ -159,6 +236,9 @@ def test_batched_family_64_instances():
           f"t {reps[0]['t_total_s']:.3f} s", flush=True)
     assert all(r["converged"] and r["rel_residual"] <= 1e-8 for r in reps)
     Ub = BS.unpack(U)
+    # the three smallest instances against the oracle's Newton step
+    smallest = sorted(range(len(specs)), key=lambda b: (specs[b]["n_cells"][0], b))[:3]
+    check_batch_newton_vs_oracle(specs, states, Ub, reps, smallest, "f32")
     for b in (0, 17, 63):
         U0, Uold, phit = states[b]
         S = gpu_solver(specs[b], vcycle_precision=pff.PF_F32)
@@ -174,8 +254,10 @@ def test_batched_family_64_instances():
         print(f"  inst {b}: batch its {reps[b]['gmres_iters']} |A| {nb}; single its {rep.gmres_iters} |A| {ns}; "
               f"tie band {band}; rel diff {e:.1e}", flush=True)
         assert abs(nb - ns) <= band
-        if nb == ns:
-            assert e <= 1e-6
+        # rounding-level ties pin phi at its old value in one solve and leave it free in the other:
+        # then the two solves differ in those constraints, not only in rounding (the three smallest
+        # instances are compared with the oracle above)
+        assert e <= (1e-6 if nb == ns else 1e-4)
 
 
 def test_batch_split_matches_oracle_and_single_instances():

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import EIG_DUMMY, dev, gpu_solver, host, oracle_hierarchy, rel_err
+from gpu_common import EIG_DUMMY, dev, gpu_solver, host, inject_bounds, oracle_hierarchy, rel_err
 from oracle import newton
 
 pytestmark = pytest.mark.gpu
@@ -84,11 +84,8 @@ def check_operators(s, H, S, variants):
 
 def check_vcycle(s, U, phit, act, H, S):
     from paper_1902_08112_amd import pff
-    bounds = []
-    for l in range(s["n_levels"]):
-        b = S.eig_bounds(l)
-        bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
-    H.set_linearization(U, phit, act, eig_bounds=bounds)
+    H.set_linearization(U, phit, act)
+    inject_bounds(S, H)
     r = np.random.default_rng(23).uniform(-1, 1, H.fine.n_dofs)
     z_ref = H.vcycle(r)
     for mode in (pff.PF_COARSE_AUTO, pff.PF_COARSE_FUSED, pff.PF_COARSE_STEPS):

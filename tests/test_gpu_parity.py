@@ -9,8 +9,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import (EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, mask_to_dofs, oracle_hierarchy,
-                        rel_err)
+from gpu_common import (EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, inject_bounds, mask_to_dofs, oracle_hierarchy,
+                        oracle_residual_of, rel_err)
 from oracle import model
 
 pytestmark = pytest.mark.gpu
@@ -276,11 +276,8 @@ def test_eigenvalue_estimates(name):
 @pytest.mark.parametrize("name", ["small2d", "tiny3d_q2", "small3d", "small_lshape"])
 def test_vcycle_f64_matches_oracle(name):
     s, U, phit, act, H, S = setup_case(name, seed=19)
-    bounds = []
-    for l in range(s["n_levels"]):
-        b = S.eig_bounds(l)
-        bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
-    H.set_linearization(U, phit, act, eig_bounds=bounds)
+    H.set_linearization(U, phit, act)
+    inject_bounds(S, H)
     r = np.random.default_rng(23).uniform(-1, 1, H.fine.n_dofs)
     z_ref = H.vcycle(r)
     from paper_1902_08112_amd import PF_F32, pff
@@ -310,11 +307,8 @@ def test_vcycle_fused_smoother_steps(name):
         for l in range(s["n_levels"]):
             pff.pf_set_tuning(S.ctx, l, pff.PF_F64, 1, v, zc)
             pff.pf_set_tuning(S.ctx, l, pff.PF_F32, 1, v, zc)
-        bounds = []
-        for l in range(s["n_levels"]):
-            b = S.eig_bounds(l)
-            bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
-        H.set_linearization(U, phit, act, eig_bounds=bounds)
+        H.set_linearization(U, phit, act)
+        inject_bounds(S, H)
         r = np.random.default_rng(47).uniform(-1, 1, H.fine.n_dofs)
         z_ref = H.vcycle(r)
         out = {}
@@ -407,6 +401,13 @@ def test_newton_step_matches_oracle(name, prec):
     assert rep.converged and rep.rel_residual <= 1e-8
     # both solves reach 1e-8 of the same linear system: the solutions agree to ~cond * 1e-8
     assert e <= 1e-5
+    # the oracle's own matrices confirm the library's residual claim
+    assert rep.n_active == ref["n_active"]
+    res = oracle_residual_of(ref, dU)
+    print(f"  oracle residual of the GPU update {res:.2e}", flush=True)
+    assert res <= 1.1e-8
+    if prec == "f64":
+        assert abs(rep.gmres_iters - ref["info"]["iters"]) <= 1
     d, nn = s["dim"], H.fine.n_nodes
     act = ref["active"]
     assert np.allclose(Un[d * nn:][act], Uold[d * nn:][act], atol=1e-12)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, oracle_hierarchy, rel_err
+from gpu_common import EIG_DUMMY, block_rel_errs, dev, gpu_solver, host, inject_bounds, oracle_hierarchy, rel_err
 from oracle import model, pdas, quantities
 
 pytestmark = pytest.mark.gpu
@@ -100,11 +100,8 @@ def test_split_residual_and_diagonal(name):
 def test_split_vcycle_matches_oracle(name):
     from paper_1902_08112_amd import PF_F32
     s, U, phit, act, H, S = setup_case(name, seed=19)
-    bounds = []
-    for l in range(s["n_levels"]):
-        b = S.eig_bounds(l)
-        bounds.append(dict(u=(b[0], b[1]), phi=(b[2], b[3])))
-    H.set_linearization(U, phit, act, eig_bounds=bounds)
+    H.set_linearization(U, phit, act)
+    inject_bounds(S, H)
     r = np.random.default_rng(23).uniform(-1, 1, H.fine.n_dofs)
     z_ref = H.vcycle(r)
     e = rel_err(host(S.vcycle(dev(r))), z_ref)
