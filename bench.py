@@ -88,7 +88,7 @@ def kernel_name(dim, degree, variant, split=False, mode=0, fused=False):
                 4: f"k_q1_split<2, double, {mode}>"}.get(variant, f"k_q1_2d<double, {mode}>")
     return {0: f"k_q1_3d<double, {mode}, 8, 8, {fused}>", 1: f"k_q1_3d<double, {mode}, 16, 4, {fused}>",
             2: f"k_q1_3d_atomic<double, {mode}>", 3: f"k_q1_3d_brick<double, {mode}>",
-            4: f"k_q1_split<3, double, {mode}>"}.get(variant, "?")
+            4: f"k_q1_split<3, double, {mode}>", 5: f"k_q1_3d_slab<double, {mode}, {fused}>"}.get(variant, "?")
 
 
 def measured_traffic(workload, kname, role="apply"):

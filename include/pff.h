@@ -304,7 +304,10 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info);
  * 256-thread bricks of cells staged through LDS with atomic scatter;
  * variant 0 / 1 = one wavefront per 8x8 / 16x4 tile of cells marching
  * through chunks of zc node planes with register carries (owner-computes,
- * deterministic).  With stress_split = PF_SPLIT_MIEHE only variants 2 and 4
+ * deterministic); variant 5 (3D) = one 256-thread workgroup per 16x16 tile of
+ * cells marching through chunks of zc node planes that stream through a ring
+ * of three LDS planes one plane ahead (global-to-LDS loads), with the same
+ * owner-computes combine (deterministic).  With stress_split = PF_SPLIT_MIEHE only variants 2 and 4
  * exist (the split's record-streaming loops).  Requires
  * pf_set_linearization; overwrites the V-cycle scratch vectors; synchronizes.
  * Q2 levels have one kernel and are skipped. */
@@ -336,7 +339,7 @@ pf_status pf_get_kernel_timing_op(pf_ctx* ctx, int op, int64_t* launches, int* c
 /* pf_get_kernel_timing_op with op = PF_KTIME_JACOBIAN. */
 pf_status pf_get_kernel_timing(pf_ctx* ctx, int* count, double* avg_s, double* min_s, double* max_s);
 /* Chebyshev smoother steps (Sec. 3.2.1) after the first one fused into the block-operator
- * apply on levels whose B~ runs as 3D Q1 marching tiles (autotuner variants 0 / 1), which
+ * apply on levels whose B~ runs as 3D Q1 marching tiles (autotuner variants 0 / 1 / 5), which
  * write every node exactly once: the step's vector update (residual, direction, iterate)
  * happens where the tile writes the node, and the separate vector pass disappears.  The
  * arithmetic per entry is the same as the separate pass's.
@@ -355,7 +358,7 @@ pf_status pf_set_smoother_fusion(pf_ctx* ctx, int mode);
  * choice ("fused") and its two step times ("step_us": unfused, fused) per block entry. */
 pf_status pf_set_level_fusion(pf_ctx* ctx, int level, int prec, int fused);
 /* Read / force the choice of one (level, prec, mode); variant -1 = size heuristic,
- * zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */
+ * 0..5 as listed at pf_autotune, zc <= 0 = heuristic chunk.  Used to persist tuning results across runs. */
 pf_status pf_get_tuning(pf_ctx* ctx, int level, int prec, int mode, int* variant, int* zc);
 pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant, int zc);
 /* JSON text of the choices and measured candidate times (microseconds per apply). */

@@ -699,7 +699,8 @@ pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U
 
 // ----------------------------------------------------------------------------------- dispatch
 // Variant per level: 0 = marching 8x8 tiles, 1 = marching 16x4 tiles, 2 = atomic,
-// 3 = LDS-staged bricks (3D; 2D maps it to 2), 4 = split cells (two work items per cell).
+// 3 = LDS-staged bricks (3D; 2D maps it to 2), 4 = split cells (two work items per cell),
+// 5 = LDS-staged marching slabs of 16x16 cells (cell_q1_slab.hip; 3D, 2D maps it to 0).
 // q1_set_tile forces a variant / z-chunk (tuning and tests); -1 restores the heuristic.
 static int64_t q1_tiles_xy(const Geom& g, int tile) {
   if (g.d == 2) return (g.nn[0] + 62) / 63;
@@ -724,6 +725,7 @@ int q1_variant(const Geom& g, int mode, int requested) {
   if (requested >= 0 && requested < kQ1Variants) {
     if (g.d == 2 && requested == 1) return 0;
     if (g.d == 2 && requested == 3) return 2;
+    if (g.d == 2 && requested == 5) return 0;
     return requested;
   }
   const int nplanes = g.nn[g.d - 1];
@@ -732,7 +734,7 @@ int q1_variant(const Geom& g, int mode, int requested) {
 
 bool q1_tiled_handles(const Geom& g, int mode, int requested) {
   const int v = q1_variant(g, mode, requested);
-  return v == 0 || v == 1;
+  return v == 0 || v == 1 || v == 5;
 }
 
 template <typename T>
@@ -743,6 +745,7 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
     return PF_ERR_UNSUPPORTED;
   }
   const int variant = q1_variant(g, mode, cp.variant);
+  if (variant == 5) return launch_q1_slab<T>(g, cp, mode, x, U, phit, mask, y, nullptr, s);
   if (variant == 4) {
     const int64_t nb = (2 * ((g.n_cells + 63) / 64) * 64 + 127) / 128;
     if (g.d == 3) {
@@ -823,7 +826,7 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
 bool q1_block_cheb_fusable(const Geom& g, const CellParams& cp) {
   if (g.d != 3 || g.p != 1 || cp.split || !cp.qcb) return false;
   const int v = q1_variant(g, MODE_BLOCK, cp.variant);
-  return v == 0 || v == 1;
+  return v == 0 || v == 1 || v == 5;
 }
 
 template <typename T>
@@ -832,6 +835,7 @@ pf_status launch_q1_block_cheb(const Geom& g, const CellParams& cp, const T* d, 
   *handled = q1_block_cheb_fusable(g, cp);
   if (!*handled || g.n_cells == 0) return PF_OK;
   const int tile = q1_variant(g, MODE_BLOCK, cp.variant);
+  if (tile == 5) return launch_q1_slab<T>(g, cp, MODE_BLOCK, d, U, phit, mask, nullptr, &cf, s);
   const int tx = tile == 1 ? 16 : 8;
   const int64_t ntx = (g.nn[0] + tx - 2) / (tx - 1), nty = (g.nn[1] + 64 / tx - 2) / (64 / tx - 1);
   const int zc = q1_chunk(g, tile, cp.zc);

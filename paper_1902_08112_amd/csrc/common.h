@@ -127,6 +127,12 @@ template <typename T>
 pf_status launch_q1_block_cheb(const Geom& g, const CellParams& cp, const T* d, const T* U, const T* phit,
                                const uint8_t* mask, const ChebFuse<T>& cf, hipStream_t s, bool* handled);
 bool q1_block_cheb_fusable(const Geom& g, const CellParams& cp);
+// 3D Q1 LDS-staged marching slabs (variant 5): G~ or B~ into y, or B~ with the fused
+// Chebyshev step when cf is non-null; q1_slab_chunk: node planes per chunk
+template <typename T>
+pf_status launch_q1_slab(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
+                         const uint8_t* mask, T* y, const ChebFuse<T>* cf, hipStream_t s);
+int q1_slab_chunk(const Geom& g, int requested_zc);
 
 // Q1 block operator coefficients: values per cell, and the per-linearization pass that writes them
 int q1_block_coef_values(int d);
@@ -143,7 +149,7 @@ pf_status launch_split_data(const Geom& g, const CellParams& cp, const double* U
 // write every node of y themselves), 2 = one thread per cell with atomics (y pre-set),
 // 3 = LDS-staged bricks of cells with atomics (3D, y pre-set), 4 = two work items
 // (displacement / phase-field rows) per cell with atomics (y pre-set).
-constexpr int kQ1Variants = 5;
+constexpr int kQ1Variants = 6;
 int q1_variant(const Geom& g, int mode, int requested);
 bool q1_tiled_handles(const Geom& g, int mode, int requested);
 // marching chunk the tiled kernels use for this level and request

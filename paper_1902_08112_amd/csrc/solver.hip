@@ -160,6 +160,9 @@ constexpr size_t kPartStride = 2 * kRedMaxBlocks + 256;
 constexpr int kHostScal = 520;
 constexpr int kKernelTimerMax = 1024;  // timed launches kept per pf_set_kernel_timing period
 
+// autotuner candidates measured per level, precision and operator
+constexpr int kTuneSlots = 20;
+
 struct LevelBuf {
   Geom g;
   double *U = nullptr, *phit = nullptr, *diag = nullptr;
@@ -179,7 +182,7 @@ struct LevelBuf {
   // cell-loop choice per [precision][mode APPLY/BLOCK]: variant and marching chunk (-1: heuristic)
   int variant[2][2] = {{-1, -1}, {-1, -1}};
   int zc[2][2] = {{-1, -1}, {-1, -1}};
-  double tune_us[2][2][16] = {};  // measured candidates (autotune report)
+  double tune_us[2][2][kTuneSlots] = {};  // measured candidates (autotune report)
   // per precision: whether the smoother's Chebyshev steps run fused into the marching-tile B~
   // (PF_FUSE_TUNED), and the autotuner's times of one step unfused / fused (us, 0 = not timed)
   bool fuse[2] = {false, false};
@@ -1675,13 +1678,15 @@ pf_status pf_get_level_info(pf_ctx* ctx, int level, pf_level_info* info) {
 }
 
 // ---------------------------------------------------------------------------------- autotuner
-// Candidates of the Q1 cell loop: (variant, chunk).  Variants 1 (16x4 tiles) and 3 (LDS bricks) are 3D only.
+// Candidates of the Q1 cell loop: (variant, chunk).  Variants 1 (16x4 tiles), 3 (LDS bricks) and 5
+// (LDS-staged slabs) are 3D only.
 // Small chunks suit levels that barely fill the chip, long ones (fewer recomputed halo
 // layers) the large levels.
 static const int kCand[][2] = {{2, -1}, {4, -1}, {3, -1}, {0, 4}, {0, 8}, {0, 16}, {0, 32}, {0, 64},
-                               {1, 4}, {1, 8}, {1, 16}, {1, 32}, {0, 2}, {0, 3}, {1, 2}};
-static const int kNCand = 15;
-static_assert(kNCand <= 16, "tune_us holds 16 candidates");
+                               {1, 4}, {1, 8}, {1, 16}, {1, 32}, {0, 2}, {0, 3}, {1, 2},
+                               {5, 16}, {5, 32}, {5, 64}};
+static const int kNCand = 18;
+static_assert(kNCand <= kTuneSlots, "tune_us holds kTuneSlots candidates");
 static const double kTuneTie = 0.03;
 
 extern "C++" {
@@ -1758,7 +1763,7 @@ static pf_status autotune_level(pf_ctx* c, int l, int reps, hipStream_t s) {
       double best = 1e300;
       int bv = -1, bz = -1;
       for (int k = 0; k < kNCand && st == PF_OK; ++k) {
-        if (((kCand[k][0] == 1 || kCand[k][0] == 3) && b.g.d != 3) ||
+        if (((kCand[k][0] == 1 || kCand[k][0] == 3 || kCand[k][0] == 5) && b.g.d != 3) ||
             (split && !(kCand[k][0] == 2 || kCand[k][0] == 4))) {
           b.tune_us[pi][mi][k] = -1.0;
           continue;
@@ -1853,7 +1858,7 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
   int pi, mi;
   PFF_TRY(tuning_index(ctx, level, prec, mode, &pi, &mi));
   if (variant < -1 || variant >= kQ1Variants || zc > 4096) {
-    set_error("variant must be in [-1, 4] and zc <= 4096");
+    set_error("variant must be in [-1, 5] and zc <= 4096");
     return PF_ERR_INVALID_ARG;
   }
   ctx->lev[level].variant[pi][mi] = variant;

@@ -122,7 +122,7 @@ def test_one_level_hierarchy(name):
 @pytest.mark.parametrize("name", ["aniso_3d", "aniso_2d", "aniso_3d_q2"])
 def test_anisotropic_ragged_meshes(name):
     s, U, phit, act, H, S = setup(name, seed=5)
-    variants = [(2, -1), (3, -1), (4, -1), (0, 3), (0, 5)] + ([(1, 3), (1, 7)] if s["dim"] == 3 else [])
+    variants = [(2, -1), (3, -1), (4, -1), (0, 3), (0, 5)] + ([(1, 3), (1, 7), (5, 3), (5, 7)] if s["dim"] == 3 else [])
     check_operators(s, H, S, variants if s["degree"] == 1 else [(None, None)])
     check_vcycle(s, U, phit, act, H, S)
     check_newton(s)

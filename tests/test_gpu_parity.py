@@ -53,12 +53,13 @@ def test_apply_f64_all_levels(name):
 @pytest.mark.parametrize("name", ["cfg1_2d_q1_32", "small3d", "small_lshape"])
 def test_apply_every_kernel_variant(name):
     """Each Q1 cell-loop shape the autotuner can pick (atomic, split cells, LDS bricks with
-    ragged edge bricks, 8x8 / 16x4 marching tiles with full and ragged chunks) matches the oracle, in both
-    operators and precisions."""
+    ragged edge bricks, 8x8 / 16x4 marching tiles and 16x16 LDS-staged slabs with full and ragged
+    chunks) matches the oracle, in both operators and precisions."""
     from paper_1902_08112_amd import pff
     s, U, phit, act, H, S = setup_case(name, seed=29)
     torch = __import__("torch")
-    variants = [(2, -1), (3, -1), (4, -1), (0, 8), (0, 3), (0, 1)] + ([(1, 8), (1, 5)] if s["dim"] == 3 else [])
+    variants = [(2, -1), (3, -1), (4, -1), (0, 8), (0, 3), (0, 1)] + (
+        [(1, 8), (1, 5), (5, 16), (5, 3), (5, 1)] if s["dim"] == 3 else [])
     for l in range(s["n_levels"]):
         x = np.random.default_rng(300 + l).uniform(-1, 1, H.levels[l].n_dofs)
         refG, refB = H.mg[l].G @ x, H.mg[l].B @ x
@@ -88,7 +89,7 @@ def test_block_apply_follows_pressure(name):
     H2 = oracle_hierarchy(s2)
     H2.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
     S.set_pressure(p2)
-    variants = [(2, -1), (4, -1), (0, 4)] + ([(3, -1), (1, 4)] if s["dim"] == 3 else [])
+    variants = [(2, -1), (4, -1), (0, 4)] + ([(3, -1), (1, 4), (5, 4)] if s["dim"] == 3 else [])
     for l in range(s["n_levels"]):
         x = np.random.default_rng(400 + l).uniform(-1, 1, H.levels[l].n_dofs)
         refG, refB, oldB = H2.mg[l].G @ x, H2.mg[l].B @ x, H.mg[l].B @ x
@@ -143,13 +144,13 @@ def test_autotune_report_and_cache(tmp_path):
     assert len(rep["levels"]) == s["n_levels"]
     for lv in rep["levels"]:
         for ch in lv["choices"]:
-            assert ch["variant"] in (0, 1, 2, 3, 4)
+            assert ch["variant"] in (0, 1, 2, 3, 4, 5)
             times = [t for v, z, t in ch["us"] if t > 0]
             assert len(times) >= 4 and min(times) > 0
             if ch["mode"] == "block":
                 # the fused-smoother choice is timed exactly on the marching-tile levels
                 assert ch["fused"] in (0, 1)
-                tiled = ch["variant"] in (0, 1)
+                tiled = ch["variant"] in (0, 1, 5)
                 assert (min(ch["step_us"]) > 0) == tiled
                 assert ch["fused"] == 0 or ch["step_us"][1] < ch["step_us"][0]
     # cached choices are restored without timing
@@ -303,7 +304,7 @@ def test_vcycle_fused_smoother_steps(name):
     V-cycle to rounding, and a Newton step converges to the oracle's update."""
     from paper_1902_08112_amd import PF_F32, PF_F64, pff
     s, U, phit, act, H, S = setup_case(name, seed=43)
-    for v, zc in [(0, 3), (1, 2)]:
+    for v, zc in [(0, 3), (1, 2), (5, 3)]:
         for l in range(s["n_levels"]):
             pff.pf_set_tuning(S.ctx, l, pff.PF_F64, 1, v, zc)
             pff.pf_set_tuning(S.ctx, l, pff.PF_F32, 1, v, zc)

@@ -43,7 +43,7 @@ def test_bench_line_small3d():
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-3, abs=1e-5)
     assert 0 < roof["frac"] < 1
     assert roof["kernel"] == d["kernels"]["jacobian"]["kernel"] and roof["bound"] == "alu"
-    assert roof["hbm_frac"] == pytest.approx(roof["bytes_per_launch"] / roof["kernel_s_mean"] / 8e12, rel=1e-3)
+    assert roof["hbm_frac"] == pytest.approx(roof["bytes_per_launch"] / roof["kernel_s_mean"] / 8e12, rel=1e-3, abs=1e-5)
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["unit"] == "DoFs/s" and cpu["cores"] == 1 and cpu["value"] > 0
     assert "8^3" in cpu["sample"]
