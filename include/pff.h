@@ -279,6 +279,18 @@ pf_status pf_extrapolate(pf_ctx* ctx, const double* d_phi_1, const double* d_phi
  * (E_s^+ = E_s, E_s^- = 0 without a split; the Miehe parts with stress_split = PF_SPLIT_MIEHE)
  * at the cell Gauss points.  out is host memory.  Synchronizes. */
 pf_status pf_energies(pf_ctx* ctx, const double* d_U, double out[2], void* stream);
+/* For callers that cannot allocate memory while they run (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): pf_energies
+ * with d_out in DEVICE memory (2 doubles: crack energy, bulk energy), enqueued
+ * on the stream without a read-back or a synchronization.  The call allocates
+ * nothing: its per-block partial sums live in a static device array of the
+ * library (16,448 bytes per GPU, held until the process ends; the array has
+ * room for any mesh, as the reduction grid is capped at 1024 blocks), whose
+ * address pf_setup resolves once per device.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (two streams or two host threads) race.
+ * Errors: PF_ERR_INVALID_ARG for NULL pointers or when the current device is
+ * not the one the context was set up on; PF_ERR_DEVICE for a launch failure. */
+pf_status pf_energies_noalloc(pf_ctx* ctx, const double* d_U, double* d_out, void* stream);
 /* Load on one face of the box: out[0..dim) = int_face (g_kappa(phi) sigma^+(u) + sigma^-(u)) n ds
  * (n the outward normal; the loading curve of Sec. 5 takes one component).
  * face = 2k for {x_k = 0}, 2k+1 for {x_k = extent_k}; only facets of active

@@ -7,6 +7,8 @@
 // evaluated at the cell's (p+1)^d Gauss points (the facet's (p+1)^(d-1)).
 // One thread per cell; per-block partial sums in a fixed grid, then one final
 // block, so the sums are deterministic.
+#include <mutex>
+
 #include "generic_cell.h"
 
 namespace pff {
@@ -287,6 +289,74 @@ pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face,
   PFF_CHECK_LAUNCH();
   PFF_HIP(hipMemcpyAsync(out, d_out, gm.d * sizeof(double), hipMemcpyDeviceToHost, s));
   PFF_HIP(hipStreamSynchronize(s));
+  return PF_OK;
+}
+
+
+// ----------------------------------------------------------------------------------- allocation-free
+// Device scratch of pf_energies_noalloc: the per-block partial sums of the energies and the two
+// final values, in a file-scope array that every GPU the library runs on holds until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): quantity_scratch_init resolves its address once per device, with that device
+// current, and the kernels take that address.  Every call on one GPU shares the array, so calls
+// that overlap on one GPU (two streams, two host threads) race; each call writes every partial it
+// reads, so nothing has to start at zero.
+constexpr int kNoAllocScratch = 2 * kQMaxBlocks + 8;  // doubles: 16,448 B
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+pf_status quantity_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device index beyond the scratch table");
+    return PF_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PF_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    return PF_ERR_DEVICE;
+  }
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return PF_OK;
+}
+
+// The energies of quantity_energies into d_out (device, 2 doubles), with the partial sums in the
+// device's static scratch: no read-back, no synchronization, no allocation.
+pf_status quantity_energies_noalloc(const Geom& gm, const CellParams& cp, double Gc, double eps, const double* U,
+                                    int device, double* d_out, hipStream_t s) {
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device >= 0 && device < kMaxDevices) part = g_scratch_ptr[device];
+  }
+  if (!part) {
+    set_error("no scratch address for this device (the context was set up on another device)");
+    return PF_ERR_DEVICE;
+  }
+  const int nb = qblocks(gm.n_cells);
+  if (2 * nb > kNoAllocScratch) {
+    set_error("energies need " + std::to_string(2 * nb) + " scratch doubles, the static scratch holds " +
+              std::to_string(kNoAllocScratch));
+    return PF_ERR_WORKSPACE;
+  }
+  if (gm.d == 2 && gm.p == 1)
+    k_energies<2, 1><<<nb, kQBlock, 0, s>>>(cp, Gc, eps, U, part);
+  else if (gm.d == 2)
+    k_energies<2, 2><<<nb, kQBlock, 0, s>>>(cp, Gc, eps, U, part);
+  else if (gm.p == 1)
+    k_energies<3, 1><<<nb, kQBlock, 0, s>>>(cp, Gc, eps, U, part);
+  else
+    k_energies<3, 2><<<nb, kQBlock, 0, s>>>(cp, Gc, eps, U, part);
+  PFF_CHECK_LAUNCH();
+  k_qfinal<<<1, kQBlock, 0, s>>>(part, nb, 2, d_out);
+  PFF_CHECK_LAUNCH();
   return PF_OK;
 }
 

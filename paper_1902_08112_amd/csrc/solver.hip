@@ -34,6 +34,9 @@ pf_status launch_cell_q2_f(const Geom&, const CellParams&, int, const float*, co
                            const uint8_t*, float*, hipStream_t, bool* handled);
 pf_status quantity_energies(const Geom& gm, const CellParams& cp, double Gc, double eps, const double* U,
                             double* d_part, double out[2], hipStream_t s);
+pf_status quantity_scratch_init(int device);
+pf_status quantity_energies_noalloc(const Geom& gm, const CellParams& cp, double Gc, double eps, const double* U,
+                                    int device, double* d_out, hipStream_t s);
 pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face, const double* U, double* d_part,
                                  double* out, hipStream_t s);
 pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
@@ -191,6 +194,7 @@ struct LevelBuf {
 
 struct pf_ctx {
   pf_mesh mesh;
+  int device = 0;  // the HIP device current at pf_setup
   Material mat;
   pf_options opt;
   std::vector<LevelBuf> lev;
@@ -1136,7 +1140,12 @@ pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double 
     set_error("workspace must be 256-byte aligned");
     return PF_ERR_WORKSPACE;
   }
+  int device = 0;
+  PFF_HIP(hipGetDevice(&device));
+  // the allocation-free entry point's scratch address on this device, resolved at set-up
+  PFF_TRY(quantity_scratch_init(device));
   pf_ctx* c = new pf_ctx();
+  c->device = device;
   c->mesh = *mesh;
   c->opt = o;
   c->vprec = o.vcycle_precision;
@@ -1627,6 +1636,23 @@ pf_status pf_energies(pf_ctx* ctx, const double* d_U, double out[2], void* strea
   const int L = (int)ctx->lev.size() - 1;
   return quantity_energies(ctx->lev[L].g, cparams(ctx, L), ctx->mat.Gc, ctx->mat.eps, d_U, ctx->qpart, out,
                            st(stream));
+}
+
+pf_status pf_energies_noalloc(pf_ctx* ctx, const double* d_U, double* d_out, void* stream) {
+  NEED_CTX();
+  if (!d_U || !d_out) {
+    set_error("U and out must be non-NULL");
+    return PF_ERR_INVALID_ARG;
+  }
+  int device = -1;
+  PFF_HIP(hipGetDevice(&device));
+  if (device != ctx->device) {
+    set_error("the current device is not the context's");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int L = (int)ctx->lev.size() - 1;
+  return quantity_energies_noalloc(ctx->lev[L].g, cparams(ctx, L), ctx->mat.Gc, ctx->mat.eps, d_U, device, d_out,
+                                   st(stream));
 }
 
 pf_status pf_boundary_traction(pf_ctx* ctx, const double* d_U, int face, double* out, void* stream) {

@@ -107,6 +107,7 @@ SIGNATURES = {
     "pf_extrapolate": (I, [VP, VP, VP, D, VP, VP]),
     "pf_set_pressure": (I, [VP, D]),
     "pf_energies": (I, [VP, VP, C.POINTER(D), VP]),
+    "pf_energies_noalloc": (I, [VP, VP, VP, VP]),
     "pf_boundary_traction": (I, [VP, VP, I, C.POINTER(D), VP]),
     "pf_get_kernel_timing": (I, [VP, C.POINTER(I), C.POINTER(D), C.POINTER(D), C.POINTER(D)]),
     "pf_get_kernel_timing_op": (I, [VP, I, C.POINTER(C.c_int64), C.POINTER(I), C.POINTER(D), C.POINTER(D),
@@ -470,6 +471,13 @@ class Solver:
         out = (D * 2)()
         _check(lib().pf_energies(self.ctx, U.data_ptr(), out, _stream()), "pf_energies")
         return out[0], out[1]
+
+    def energies_noalloc(self, U, out):
+        """pf_energies_noalloc: (crack energy, bulk energy) into the device tensor out (2 FP64),
+        asynchronous on the current stream, with the library's static scratch (no allocation)."""
+        assert out.dtype == self.torch.float64 and out.numel() >= 2 and out.is_cuda
+        _check(lib().pf_energies_noalloc(self.ctx, U.data_ptr(), out.data_ptr(), _stream()), "pf_energies_noalloc")
+        return out
 
     def boundary_traction(self, U, face):
         """int over box face `face` (2k: x_k = 0, 2k+1: x_k = extent_k) of g(phi) sigma(u) n."""
