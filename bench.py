@@ -436,8 +436,10 @@ def main():
         extra = 0.0
     vj = pff.pf_get_tuning(S.ctx, L, pff.PF_F64, 0)[0]
     jname = kernel_name(s["dim"], s["degree"], vj, mat_split, 0)
-    # the records make the split apply HBM-bound (flop/B below the FP64 ridge of 9.8)
-    jbound = "hbm" if split else "alu"
+    # the binding roof is the one with the longer time at peak (flop/B against the FP64 ridge of 9.8):
+    # FP64 VALU for the 3D applies, HBM for 2D Q1 and for the split's record-streaming Q1 apply
+    jbound = None if flops is None else (
+        "alu" if flops / FP64_PEAK_TFLOPS / 1e12 >= (rule_bytes + extra) / HBM_PEAK_GBS / 1e9 else "hbm")
     jac = kernel_entry(kt_base, a.steps, flops, rule_bytes + (extra or 0.0), jbound, jname, "apply",
                        extra_bytes=extra or 0.0, t_fallback=t_apply)
     jac.update({"apply_call_s": t_apply, "apply_call_f32_s": t_apply32,

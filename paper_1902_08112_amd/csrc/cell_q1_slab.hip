@@ -29,6 +29,7 @@ constexpr int kSPlane = kSNX * kSNY;              // 289
 constexpr int kSThreads = kSX * kSY;              // 256
 constexpr int kSWaves = kSThreads / 64;           // 4
 constexpr int kSMaskPad = 292;                    // mask bytes per plane, dword-padded
+constexpr int kSPlanePad = 320;                   // values per LDS plane: 289 padded to whole wavefronts
 
 template <int MODE>
 struct SlabFields {
@@ -49,18 +50,21 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 // Streaming of one node plane of one field into LDS rows of 17 values with global_load_lds, a
 // dword per lane: the plane's dword e (row jj = e / ROW) comes from the lattice node
-// (gx0 + ii, gy0 + jj) of the plane and lands at LDS dword e.  The per-lane byte offsets
-// within a plane (and whether the node is in the lattice) are the same for every field and
-// every plane, so they are computed once; the per-field, per-plane base is uniform.  Lanes
-// whose node lies outside the lattice load nothing: those slots are only ever read by cells
-// outside the mesh, which contribute nothing.
+// (gx0 + ii, gy0 + jj) of the plane and lands at LDS dword e.  The LDS plane is padded to whole
+// wavefronts (kSPlanePad values), so every lane of a streaming wavefront loads: a lane past the
+// plane fills padding, and a lane whose node lies outside the lattice reads the plane's node
+// (0, 0) into a slot that only cells outside the mesh ever read (they contribute nothing).  The
+// per-lane byte offsets within a plane are the same for every field and every plane, so they are
+// computed once; the per-field, per-plane base is uniform.
 template <typename T>
 struct PlaneStream {
   static constexpr int W = (int)(sizeof(T) / 4);         // dwords per value
   static constexpr int ROW = kSNX * W;                   // dwords per row
   static constexpr int TOT = kSNY * ROW;                 // dwords per plane
-  static constexpr int R = (TOT + kSThreads - 1) / kSThreads;
-  uint32_t off[R];                                       // byte offset within the plane, or ~0u
+  static constexpr int TOTW = (TOT + 63) / 64 * 64;      // streamed dwords (whole wavefronts)
+  static constexpr int R = (TOTW + kSThreads - 1) / kSThreads;
+  static_assert(TOTW <= kSPlanePad * W, "padded LDS plane");
+  uint32_t off[R];                                       // byte offset within the plane
   __device__ __forceinline__ void init(int gx0, int gy0, const CellParams& cp, int tid) {
     const int wave = tid >> 6, lane = tid & 63;
 #pragma unroll
@@ -70,22 +74,20 @@ struct PlaneStream {
       const int ii = col / W;
       const int gx = gx0 + ii, gy = gy0 + jj;
       const bool ok = e < TOT && gx >= 0 && gx < cp.nn[0] && gy >= 0 && gy < cp.nn[1];
-      off[r] = ok ? (uint32_t)(((int64_t)gx + (int64_t)gy * cp.ns[1]) * (int64_t)sizeof(T) + 4 * (col - ii * W))
-                  : ~0u;
+      off[r] = ok ? (uint32_t)(((int64_t)gx + (int64_t)gy * cp.ns[1]) * (int64_t)sizeof(T) + 4 * (col - ii * W)) : 0u;
     }
   }
-  // plane base (uniform): the field's array at node plane kz
-  __device__ __forceinline__ void fetch(const T* __restrict__ plane, T* dst, int tid) const {
-    const int wave = tid >> 6;
+  // plane: the field's array at node plane kz (uniform); wave: the wavefront index (uniform)
+  __device__ __forceinline__ void fetch(const T* __restrict__ plane, T* dst, int wave) const {
     const char* base = reinterpret_cast<const char*>(plane);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int e0 = r * kSThreads + wave * 64;  // wave-uniform
+      const int e0 = r * kSThreads + wave * 64;
       uint32_t o = off[r];
       // an opaque copy per call: keeps the compiler from hoisting 64-bit addresses out of the
       // layer loop (it would hold, or spill, one pair per load); uniform base + 32-bit offset
       __asm__ __volatile__("" : "+v"(o));
-      if (e0 < TOT && o != ~0u)
+      if (e0 < TOTW)
         __builtin_amdgcn_global_load_lds(base + o, (lds_void*)(reinterpret_cast<char*>(dst) + 4 * e0), 4, 0, 0);
     }
   }
@@ -172,11 +174,13 @@ __device__ __forceinline__ void val3_layer(const T f[8], int h, T v[4]) {
 
 // Phase-field rows of G~ (the coupled rows of cell3_phi in q1_cell.h) with the Gauss points taken
 // one z-layer at a time, the corners of u, du and phi re-read from LDS for each layer, so that the
-// gradient tables of u and of du are never both whole in registers.
+// gradient tables of u and of du are never both whole in registers (FP64: the whole-cell form
+// spills at two waves per SIMD and is 24% slower on 256^3; FP32 keeps the whole-cell form, which
+// needs fewer operations and does not spill).
 //   f(q) = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) dphi + phi ((1-kappa) sigma(u):e(du) + 2 p div du)
 //   out[a] = sum_q f(q) JxW N_a(q) + G_c eps grad dphi . grad N_a JxW
 template <typename T, int NF>
-__device__ __forceinline__ void phi_rows_layers(const Consts<T>& k, const T (*plo)[kSPlane], const T (*phi_)[kSPlane],
+__device__ __forceinline__ void phi_rows_layers(const Consts<T>& k, const T (*plo)[kSPlanePad], const T (*phi_)[kSPlanePad],
                                                 int ln, const uint8_t mk[8], int u0, const T dp[8], T out[8]) {
   T fv[8];
 #pragma unroll
@@ -253,9 +257,9 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   static_assert(!CHEB || MODE == MODE_BLOCK, "the fused Chebyshev step follows the block operator");
   using F = SlabFields<MODE>;
   constexpr bool COUPLE = (MODE == MODE_APPLY);
-  __shared__ T sv[3][F::NF][kSPlane];
+  __shared__ T sv[3][F::NF][kSPlanePad];
   __shared__ uint8_t sm[3][kSMaskPad];
-  __shared__ T sx[2][kSWaves][kSX][8];  // cross-wave y exchange (double-buffered by layer parity)
+  __shared__ T sx[2][kSWaves - 1][kSX][8];  // cross-wave y exchange (double-buffered by layer parity)
 
   const int64_t t = xcd_tile_s(blockIdx.x, gridDim.x);
   const int bz = (int)(t % nzc);
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   const int by = (int)(t / ((int64_t)nzc * ntx));
   const int tid = threadIdx.x;
   const int i = tid % kSX, j = tid / kSX;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool first_row = (j & 3) == 0, last_row = (j & 3) == 3;
   const int gx0 = bx * (kSX - 1) - 1, gy0 = by * (kSY - 1) - 1;
   const int cx = gx0 + i, cy = gy0 + j;
@@ -294,17 +298,17 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
     const int slot = (kz + 3) % 3;
     const int64_t zo = (int64_t)kz * sz;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) ps.fetch(x + c * nn + zo, &sv[slot][c][0], tid);
+    for (int c = 0; c < 4; ++c) ps.fetch(x + c * nn + zo, &sv[slot][c][0], wave);
     if constexpr (COUPLE) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ps.fetch(U + c * nn + zo, &sv[slot][F::U0 + c][0], tid);
+      for (int c = 0; c < 4; ++c) ps.fetch(U + c * nn + zo, &sv[slot][F::U0 + c][0], wave);
     }
-    ps.fetch(phit + zo, &sv[slot][F::PT][0], tid);
+    ps.fetch(phit + zo, &sv[slot][F::PT][0], wave);
     const uint8_t* mp = mask + zo;
     uint32_t o0 = moff[0], o1 = moff[1];
     __asm__ __volatile__("" : "+v"(o0), "+v"(o1));
-    m0 = o0 != ~0u ? mp[o0] : (uint8_t)0xFF;
-    m1 = o1 != ~0u ? mp[o1] : (uint8_t)0xFF;
+    m0 = mp[o0 != ~0u ? o0 : 0u];
+    m1 = mp[o1 != ~0u ? o1 : 0u];
   };
   auto put_mask = [&](int kz, uint8_t m0, uint8_t m1) {
     const int slot = (kz + 3) % 3;
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
       for (int c = 0; c < 3; ++c) {
         T X1[2];
         combine_xy<T>(outu[c], first_row, Y[c], X1);
-        if (last_row) {
+        if (last_row && wave < kSWaves - 1) {
           sx[par][wave][i][2 * c] = X1[0];
           sx[par][wave][i][2 * c + 1] = X1[1];
         }
@@ -393,7 +397,23 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
           for (int q = 0; q < 8; ++q) cq[q] = qcb[q * cp.n_cells + cid];
           cell3_phi_stored<T>(kc, dp, cq, outp);
         } else {
-          phi_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, dp, outp);
+          if constexpr (sizeof(T) == 8) {
+            // FP64: one Gauss layer at a time (the whole-cell tables would spill at 2 waves/SIMD)
+            phi_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, dp, outp);
+          } else {
+            // FP32 fits the whole-cell tables (fewer operations than the layered form)
+            T du[3][8], uu[3][8], ph[8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
+#pragma unroll
+              for (int a = 0; a < 8; ++a)
+                if (mk[a] & (1 << c)) du[c][a] = T(0);
+              corners<T>(&sv[lo][F::U0 + c][0], &sv[hi][F::U0 + c][0], ln, uu[c]);
+            }
+            corners<T>(&sv[lo][F::U0 + 3][0], &sv[hi][F::U0 + 3][0], ln, ph);
+            cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+          }
         }
       } else {
 #pragma unroll
@@ -401,7 +421,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
       }
       T X1[2];
       combine_xy<T>(outp, first_row, Y[3], X1);
-      if (last_row) {
+      if (last_row && wave < kSWaves - 1) {
         sx[par][wave][i][6] = X1[0];
         sx[par][wave][i][7] = X1[1];
       }

@@ -42,6 +42,7 @@ def test_bench_line_small3d():
     # frac and achieved are rounded separately (5 and 2-4 decimals)
     assert roof["frac"] == pytest.approx(roof["achieved"] / roof["peak"], rel=1e-3, abs=1e-5)
     assert 0 < roof["frac"] < 1
+    # small3d is a 3D Q1 mesh: its Jacobian apply is bound by FP64 VALU
     assert roof["kernel"] == d["kernels"]["jacobian"]["kernel"] and roof["bound"] == "alu"
     assert roof["hbm_frac"] == pytest.approx(roof["bytes_per_launch"] / roof["kernel_s_mean"] / 8e12, rel=1e-3, abs=1e-5)
     cpu = d["cpu_baseline"]
