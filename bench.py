@@ -203,6 +203,9 @@ def run_batch(a):
             _, reps = BS.newton_step(U, Uold, phit)
         return reps
 
+    # one step sets the linearization; the autotuner then picks the cell-loop shape per level
+    steps(1, pff.PF_F32)
+    tuning = BS.autotune(reps=10) if not a.no_tune else None
     res = {}
     for prec in (pff.PF_F32, pff.PF_F64):
         steps(max(1, a.warmup), prec)
@@ -253,10 +256,12 @@ def run_batch(a):
         "gmres_iters_min_max": [min(r["gmres_iters"] for r in reps32), max(r["gmres_iters"] for r in reps32)],
         "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": "batched FP64 Jacobian apply, finest levels of all instances",
+                     "kernel": "batched FP64 Jacobian apply, finest levels of all instances (shape "
+                               + ("-1" if tuning is None else str(tuning[-1]["choices"][0]["shape"])) + ")",
                      "bytes_per_launch": bytes_, "flop_per_launch": FLOP_PER_CELL[(2, 1)] * n_cells,
                      "apply_s": t_apply},
         "cpu_baseline": None,
+        "tuning_fine_level": None if tuning is None else tuning[-1]["choices"],
     }
     BS.close()
     if not a.no_cpu:

@@ -452,6 +452,26 @@ pf_status pf_batch_set_vcycle_precision(pf_batch* b, int prec);
 /* Graph replay of the batched V-cycle (default on; see pf_set_graphs).  Its
  * coefficients are read from device memory, so one capture serves every step. */
 pf_status pf_batch_set_graphs(pf_batch* b, int enable);
+/* Autotuner of the batched Q1 cell loop (the tensor-product apply of Sec. 4.1, for every
+ * instance at once).  For every level, precision and operator (mode 0: G~, 1: block B~) it
+ * times `reps` applies of each candidate shape and keeps the first within 3% of the fastest:
+ *   shape -1  one grid-stride launch over the cells of all instances (each cell finds its
+ *             instance by a search of the packed offsets), atomic scatter;
+ *   shape  2  a work table of (instance, 64 consecutive cells) items, atomic scatter;
+ *   shape  0  a work table of (instance, marching tile) items: 3D 8x8 tiles / 2D 64-cell rows
+ *             marching through zc node planes (rows), every node written once;
+ *   shape  1  (3D) 16x4 marching tiles.
+ * A table item's instance is uniform over its workgroup; the workgroups of one launch loop over
+ * the table.  Candidates: -1, 2, 0 with zc = 4, 8, 16, 32, 1 with zc = 4, 8, 16 (Q1 only; the
+ * split and Q2 keep shape -1).  Requires pf_batch_set_linearization; overwrites the V-cycle
+ * scratch vectors; drops the captured V-cycles; synchronizes. */
+pf_status pf_batch_autotune(pf_batch* b, int reps, void* stream);
+/* The choice of one (level, prec, mode): shape and zc; us (NULL or 9 doubles): the autotuner's
+ * time per apply of each candidate in the order above (-1 where not timed). */
+pf_status pf_batch_get_tuning(pf_batch* b, int level, int prec, int mode, int* shape, int* zc, double* us);
+/* Force a shape (-1, 0, 1, 2) and chunk for one (level, prec, mode), e.g. to restore cached
+ * tuning; PF_ERR_WORKSPACE if its table exceeds the room set aside (chunks below 4). */
+pf_status pf_batch_set_tuning(pf_batch* b, int level, int prec, int mode, int shape, int zc);
 /* One Newton/active-set step (Algorithm 1) of every instance; reps: n reports
  * (may be NULL).  FGMRES advances all unconverged instances in lockstep and
  * stops each at its own tolerance.  Synchronizes.  PF_ERR_NOT_CONVERGED if any

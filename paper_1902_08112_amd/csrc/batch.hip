@@ -14,6 +14,13 @@
 // (Chebyshev coefficients, CG and Arnoldi coefficients) are device arrays.
 // FGMRES advances all unconverged instances in lockstep with per-instance
 // Hessenberg matrices on the host; each instance stops at its own tolerance.
+//
+// The Q1 cell loop also runs from a per-level work table of (instance, tile) items
+// (pf_batch_autotune picks the shape per level, precision and operator): one launch per
+// stage whose workgroups loop over the table, each item one marching tile of one instance
+// (the single-instance bodies of q1_tiles.h, no atomics) or 64 consecutive cells of one
+// instance with atomic scatter.  The instance of an item is uniform across its workgroup,
+// so its geometry and material come through scalar loads, with no per-cell search.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -24,6 +31,7 @@
 #include "generic_cell.h"
 #include "grid_ops.h"
 #include "q1_cell.h"
+#include "q1_tiles.h"
 
 namespace pff {
 
@@ -172,6 +180,88 @@ static pf_status b_cell(const BView& v, int mode, const T* x, const T* U, const 
   if (v.d == 2 && v.p == 2) return b_cell_dp<2, 2, T>(v, mode, x, U, phit, mask, y, s);
   if (v.d == 3 && v.p == 1) return b_cell_dp<3, 1, T>(v, mode, x, U, phit, mask, y, s);
   return b_cell_dp<3, 2, T>(v, mode, x, U, phit, mask, y, s);
+}
+
+// ---------------------------------------------------------------------------- work-table cell loop
+// Shapes of a work item (kBShape*): 64 consecutive cells of one instance with atomic scatter into y
+// preset to Pi_C x; a 3D 8x8 or 16x4 marching tile / 2D 64-cell marching row of one instance
+// (every node written once).  items[w] = {instance, tile index within the instance}; the
+// workgroups loop over the table (a grid of at most kBItemsGrid workgroups).
+constexpr int kBShapeAtomic = 2, kBShapeMarch = 0, kBShapeMarch16 = 1;
+constexpr int kBItemsGrid = 4096;
+
+template <int D, typename T, int MODE, int SHAPE>
+__global__ __launch_bounds__(64) void k_b_items(BView v, const int2* __restrict__ items, int n_items, int zc,
+                                                const T* __restrict__ x, const T* __restrict__ U,
+                                                const T* __restrict__ phit, const uint8_t* __restrict__ mask,
+                                                T* __restrict__ y) {
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const int2 it = items[w];
+    const int b = it.x, tl = it.y;
+    const CellParams cp = v.inst[b].cp;
+    const int64_t dof = v.dof_off[b], node = v.node_off[b];
+    const T* xo = x + dof;
+    const T* Uo = U + dof;
+    const T* po = phit + node;
+    const uint8_t* mo = mask + node;
+    T* yo = y + dof;
+    if constexpr (SHAPE == kBShapeAtomic) {
+      const int64_t lc = (int64_t)tl * 64 + threadIdx.x;
+      if (lc < cp.n_cells) {
+        const int cx = (int)(lc % cp.N[0]);
+        const int cy = (int)((lc / cp.N[0]) % cp.N[1]);
+        const int cz = D == 3 ? (int)(lc / ((int64_t)cp.N[0] * cp.N[1])) : 0;
+        if (!cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) {
+          const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
+          q1_cell_atomic<D, T, MODE == MODE_APPLY>(cp, g0, xo, Uo, po, mo, yo);
+        }
+      }
+    } else if constexpr (D == 3) {
+      constexpr int TX = SHAPE == kBShapeMarch16 ? 16 : 8, TY = 64 / TX;
+      const int ntx = (cp.nn[0] + TX - 2) / (TX - 1);
+      const int nzc = (cp.nn[2] + zc - 1) / zc;
+      const int bz = tl % nzc, bx = (tl / nzc) % ntx, by = tl / (nzc * ntx);
+      q1_tile3<T, MODE, TX, TY, false, false>(cp, zc, bx, by, bz, xo, Uo, po, mo, yo, ChebFuse<T>{});
+    } else {
+      const int nyc = (cp.nn[1] + zc - 1) / zc;
+      q1_tile2<T, MODE, false>(cp, zc, tl / nyc, tl % nyc, xo, Uo, po, mo, yo);
+    }
+  }
+}
+
+// items of one instance for a shape (and chunk zc of the marching shapes)
+static int64_t b_items_of(const CellParams& cp, int d, int shape, int zc) {
+  if (shape == kBShapeAtomic) return (cp.n_cells + 63) / 64;
+  if (d == 3) {
+    const int tx = shape == kBShapeMarch16 ? 16 : 8, ty = 64 / tx;
+    return (int64_t)((cp.nn[0] + tx - 2) / (tx - 1)) * ((cp.nn[1] + ty - 2) / (ty - 1)) * ((cp.nn[2] + zc - 1) / zc);
+  }
+  return (int64_t)((cp.nn[0] + 62) / 63) * ((cp.nn[1] + zc - 1) / zc);
+}
+
+template <int D, typename T, int SHAPE>
+static pf_status b_items_launch(const BView& v, int mode, const int2* items, int n, int zc, const T* x, const T* U,
+                                const T* phit, const uint8_t* mask, T* y, hipStream_t s) {
+  const int grid = std::min(n, kBItemsGrid);
+  if (mode == MODE_APPLY)
+    k_b_items<D, T, MODE_APPLY, SHAPE><<<grid, 64, 0, s>>>(v, items, n, zc, x, U, phit, mask, y);
+  else
+    k_b_items<D, T, MODE_BLOCK, SHAPE><<<grid, 64, 0, s>>>(v, items, n, zc, x, U, phit, mask, y);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+template <typename T>
+static pf_status b_items(const BView& v, int mode, int shape, const int2* items, int n, int zc, const T* x,
+                         const T* U, const T* phit, const uint8_t* mask, T* y, hipStream_t s) {
+  if (n <= 0) return PF_OK;
+  if (v.d == 3) {
+    if (shape == kBShapeAtomic) return b_items_launch<3, T, kBShapeAtomic>(v, mode, items, n, zc, x, U, phit, mask, y, s);
+    if (shape == kBShapeMarch16) return b_items_launch<3, T, kBShapeMarch16>(v, mode, items, n, zc, x, U, phit, mask, y, s);
+    return b_items_launch<3, T, kBShapeMarch>(v, mode, items, n, zc, x, U, phit, mask, y, s);
+  }
+  if (shape == kBShapeAtomic) return b_items_launch<2, T, kBShapeAtomic>(v, mode, items, n, zc, x, U, phit, mask, y, s);
+  return b_items_launch<2, T, kBShapeMarch>(v, mode, items, n, zc, x, U, phit, mask, y, s);
 }
 
 // ---------------------------------------------------------------------------- DoF-wise kernels
@@ -419,6 +509,12 @@ namespace {
 
 constexpr int kSegBlocks = 16;  // blocks per segment in segmented reductions
 
+// autotuner candidates of the batched Q1 cell loop: (shape, chunk); -1 = the grid-stride kernel over
+// all cells (also the only shape with the split and on Q2)
+static const int kBCand[][2] = {{-1, 0}, {kBShapeAtomic, 0}, {kBShapeMarch, 4}, {kBShapeMarch, 8}, {kBShapeMarch, 16},
+                                {kBShapeMarch, 32}, {kBShapeMarch16, 4}, {kBShapeMarch16, 8}, {kBShapeMarch16, 16}};
+static const int kBNCand = 9;
+
 struct BLevel {
   std::vector<BInst> h_inst;
   std::vector<int64_t> h_dof, h_node, h_cell;
@@ -435,6 +531,14 @@ struct BLevel {
   double* d_coef_c = nullptr;  // [coarse_degree][B][4] (level 0)
   std::vector<double> eig;     // [B][4]
   std::vector<double> eig_fix; // [B][4]: bounds fixed by pf_batch_set_eig_bounds (0: estimate)
+  // cell-loop shape per [precision][operator] (-1: grid-stride over all cells) with its chunk and
+  // work table (items[pi][mi], capacity item_cap each); tune_us: the autotuner's timings
+  int shape[2][2] = {{-1, -1}, {-1, -1}};
+  int zc[2][2] = {{0, 0}, {0, 0}};
+  int n_items[2][2] = {{0, 0}, {0, 0}};
+  int2* items[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int64_t item_cap = 0;
+  double tune_us[2][2][16] = {};
   int d = 0, p = 0, B = 0;
   int split = PF_SPLIT_NONE;
   BView view() const {
@@ -489,6 +593,14 @@ struct pf_batch {
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool use_graphs = true;
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k) {
+      if (vexec[k]) (void)hipGraphExecDestroy(vexec[k]);
+      if (vgraph[k]) (void)hipGraphDestroy(vgraph[k]);
+      vexec[k] = nullptr;
+      vgraph[k] = nullptr;
+    }
+  }
   ~pf_batch() {
     for (int k = 0; k < 2; ++k) {
       if (vexec[k]) hipGraphExecDestroy(vexec[k]);
@@ -615,6 +727,19 @@ size_t bcarve(pf_batch* c, const pf_mesh* meshes, int n, const pf_options& o, ch
     bl.vd = cv.take<double>(nd);
     bl.d_coef_s = cv.take<double>((size_t)o.cheb_degree * n * 4);
     bl.d_coef_c = cv.take<double>((size_t)o.coarse_degree * n * 4);
+    // work tables: room for the largest table of any autotuner candidate
+    int64_t cap = 0;
+    if (bl.p == 1) {
+      for (int k = 0; k < kBNCand; ++k) {
+        if (kBCand[k][0] < 0 || (kBCand[k][0] == kBShapeMarch16 && d != 3)) continue;
+        int64_t m = 0;
+        for (int b = 0; b < n; ++b) m += b_items_of(bl.h_inst[b].cp, d, kBCand[k][0], kBCand[k][1]);
+        cap = std::max(cap, m);
+      }
+    }
+    bl.item_cap = cap;
+    for (int pi = 0; pi < 2; ++pi)
+      for (int mi = 0; mi < 2; ++mi) bl.items[pi][mi] = cap ? cv.take<int2>((size_t)cap) : nullptr;
     bl.eig.assign(4 * n, 1.0);
     bl.eig_fix.assign(4 * n, 0.0);
   }
@@ -679,6 +804,19 @@ pf_status b_fill(T* y, T v, int64_t n, hipStream_t s) {
 pf_status bapply(pf_batch* c, int l, int prec, int mode, const void* x, void* y, hipStream_t s) {
   BLevel& bl = c->lev[l];
   const BView v = bl.view();
+  const int pi = prec == PF_F64 ? 0 : 1;
+  if ((mode == MODE_APPLY || mode == MODE_BLOCK) && !bl.split && bl.p == 1 && bl.shape[pi][mode] >= 0) {
+    const int sh = bl.shape[pi][mode];
+    // marching tiles write every node; one thread per cell adds into Pi_C x
+    if (prec == PF_F64) {
+      if (sh == kBShapeAtomic) PFF_TRY(b_init_constrained<double>(bl, (double*)y, (const double*)x, s));
+      return b_items<double>(v, mode, sh, bl.items[pi][mode], bl.n_items[pi][mode], bl.zc[pi][mode], (const double*)x,
+                             bl.U, bl.phit, bl.mask, (double*)y, s);
+    }
+    if (sh == kBShapeAtomic) PFF_TRY(b_init_constrained<float>(bl, (float*)y, (const float*)x, s));
+    return b_items<float>(v, mode, sh, bl.items[pi][mode], bl.n_items[pi][mode], bl.zc[pi][mode], (const float*)x,
+                          bl.U32, bl.phit32, bl.mask, (float*)y, s);
+  }
   if (prec == PF_F64) {
     if (mode == MODE_APPLY || mode == MODE_BLOCK)
       PFF_TRY(b_init_constrained<double>(bl, (double*)y, (const double*)x, s));
@@ -1386,6 +1524,125 @@ pf_status pf_batch_set_eig_bounds(pf_batch* bt, int level, int inst, const doubl
   // the Chebyshev coefficients live in device memory (captured V-cycles read them there)
   if (bt->has_lin) PFF_TRY(upload_cheb(bt, nullptr));
   return PF_OK;
+}
+
+// the work table of level l, precision index pi and operator mi for a shape and chunk
+static pf_status b_build_items(pf_batch* c, int l, int pi, int mi, int shape, int zc, hipStream_t s) {
+  BLevel& bl = c->lev[l];
+  bl.shape[pi][mi] = -1;
+  bl.zc[pi][mi] = 0;
+  bl.n_items[pi][mi] = 0;
+  if (shape < 0) return PF_OK;
+  if (bl.p != 1 || bl.split || !bl.items[pi][mi] || (shape == kBShapeMarch16 && bl.d != 3) ||
+      (shape != kBShapeAtomic && zc < 1)) {
+    set_error("batched cell loop: no work table of this shape on this level");
+    return PF_ERR_UNSUPPORTED;
+  }
+  std::vector<int2> h;
+  for (int b = 0; b < bl.B; ++b) {
+    const int64_t m = b_items_of(bl.h_inst[b].cp, bl.d, shape, zc);
+    for (int64_t k = 0; k < m; ++k) h.push_back(make_int2(b, (int)k));
+  }
+  if ((int64_t)h.size() > bl.item_cap || h.size() > (size_t)0x7fffffff) {
+    set_error("batched cell loop: the work table does not fit (chunk below the autotuner's smallest?)");
+    return PF_ERR_WORKSPACE;
+  }
+  if (!h.empty()) {
+    PFF_HIP(hipMemcpyAsync(bl.items[pi][mi], h.data(), h.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    PFF_HIP(hipStreamSynchronize(s));
+  }
+  bl.shape[pi][mi] = shape;
+  bl.zc[pi][mi] = shape == kBShapeAtomic ? 0 : zc;
+  bl.n_items[pi][mi] = (int)h.size();
+  return PF_OK;
+}
+
+pf_status pf_batch_autotune(pf_batch* bt, int reps, void* stream) {
+  NEED_BATCH();
+  if (!bt->has_lin) {
+    set_error("no linearization point: call pf_batch_set_linearization");
+    return PF_ERR_INVALID_ARG;
+  }
+  if (reps < 1 || reps > 10000) {
+    set_error("reps must be in [1, 10000]");
+    return PF_ERR_INVALID_ARG;
+  }
+  hipStream_t s = bst(stream);
+  bt->drop_graphs();
+  hipEvent_t e0, e1;
+  PFF_HIP(hipEventCreate(&e0));
+  PFF_HIP(hipEventCreate(&e1));
+  pf_status st = PF_OK;
+  for (int l = 0; l < bt->L && st == PF_OK; ++l) {
+    BLevel& bl = bt->lev[l];
+    if (bl.p != 1 || bl.split) continue;
+    for (int pi = 0; pi < 2 && st == PF_OK; ++pi) {
+      const int prec = pi == 0 ? PF_F64 : PF_F32;
+      st = prec == PF_F64 ? vec_fill<double>((double*)bl.vb, 1.0, bl.n_dofs, s)
+                          : vec_fill<float>((float*)bl.vb, 1.0f, bl.n_dofs, s);
+      for (int mi = 0; mi < 2 && st == PF_OK; ++mi) {
+        double best = 1e300;
+        for (int k = 0; k < kBNCand && st == PF_OK; ++k) {
+          bl.tune_us[pi][mi][k] = -1.0;
+          if (kBCand[k][0] == kBShapeMarch16 && bl.d != 3) continue;
+          st = b_build_items(bt, l, pi, mi, kBCand[k][0], kBCand[k][1], s);
+          for (int w = 0; w < 2 && st == PF_OK; ++w) st = bapply(bt, l, prec, mi, bl.vb, bl.vt, s);
+          if (st != PF_OK) break;
+          float ms = 0.f;
+          if (hipEventRecord(e0, s) != hipSuccess) st = PF_ERR_DEVICE;
+          for (int r = 0; r < reps && st == PF_OK; ++r) st = bapply(bt, l, prec, mi, bl.vb, bl.vt, s);
+          if (st != PF_OK) break;
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            set_error("batched autotune timing failed");
+            st = PF_ERR_DEVICE;
+            break;
+          }
+          bl.tune_us[pi][mi][k] = 1e3 * ms / reps;
+          best = std::min(best, bl.tune_us[pi][mi][k]);
+        }
+        if (st != PF_OK) break;
+        // the earliest candidate within 3% of the fastest (timing noise does not flip the choice)
+        int pick = 0;
+        for (int k = 0; k < kBNCand; ++k)
+          if (bl.tune_us[pi][mi][k] > 0.0 && bl.tune_us[pi][mi][k] <= best * 1.03) {
+            pick = k;
+            break;
+          }
+        st = b_build_items(bt, l, pi, mi, kBCand[pick][0], kBCand[pick][1], s);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+pf_status pf_batch_get_tuning(pf_batch* bt, int level, int prec, int mode, int* shape, int* zc, double* us) {
+  NEED_BATCH();
+  if (level < 0 || level >= bt->L || (prec != PF_F64 && prec != PF_F32) || (mode != 0 && mode != 1) || !shape ||
+      !zc) {
+    set_error("bad level, precision, mode or output pointer");
+    return PF_ERR_INVALID_ARG;
+  }
+  const BLevel& bl = bt->lev[level];
+  const int pi = prec == PF_F64 ? 0 : 1;
+  *shape = bl.shape[pi][mode];
+  *zc = bl.zc[pi][mode];
+  if (us)
+    for (int k = 0; k < kBNCand; ++k) us[k] = bl.tune_us[pi][mode][k];
+  return PF_OK;
+}
+
+pf_status pf_batch_set_tuning(pf_batch* bt, int level, int prec, int mode, int shape, int zc) {
+  NEED_BATCH();
+  if (level < 0 || level >= bt->L || (prec != PF_F64 && prec != PF_F32) || (mode != 0 && mode != 1) ||
+      shape < -1 || shape > kBShapeAtomic) {
+    set_error("bad level, precision, mode or shape");
+    return PF_ERR_INVALID_ARG;
+  }
+  bt->drop_graphs();
+  return b_build_items(bt, level, prec == PF_F64 ? 0 : 1, mode, shape, zc, nullptr);
 }
 
 pf_status pf_batch_set_graphs(pf_batch* bt, int enable) {

@@ -1,0 +1,242 @@
+// Marching-tile bodies of the Q1 cell loop (Sec. 4.1), shared by the single-instance kernels
+// (cell_q1.hip) and the batched work-table kernel (batch.hip).
+//
+// One wavefront per tile.  3D: a TX x TY patch of cells (one cell per lane) marches along z
+// through a chunk of node planes; 2D: 64 cells along x march along y.  Each lane owns the node
+// at the lower corner of its cell.  Per cell layer the 2^d corner contributions are combined
+// without atomics: along x with a one-lane shuffle, along y (3D) with a TX-lane shuffle, and
+// along the marching axis with a register carry from the previous layer.  Tiles overlap by one
+// cell column in x and y (and one layer per chunk), so a lane with i = 0 or j = 0 computes a halo
+// cell and owns nothing; every node is written exactly once, with plain stores, including the
+// identity rows of the constrained DoFs.  The result is deterministic.
+#pragma once
+
+#include "q1_cell.h"
+
+namespace pff {
+
+// combine the corner contributions of a TX x TY patch: value at the lane's own node of
+// plane k (layers k-1 and k) and the carry into plane k+1
+template <typename T, int TX>
+__device__ __forceinline__ void combine3(const T out[8], T carry, T& val, T& ncarry) {
+  T X[2][2];
+#pragma unroll
+  for (int az = 0; az < 2; ++az)
+#pragma unroll
+    for (int ay = 0; ay < 2; ++ay) X[ay][az] = out[2 * ay + 4 * az] + __shfl_up(out[1 + 2 * ay + 4 * az], 1, TX);
+  const T y0 = X[0][0] + __shfl_up(X[1][0], TX, 64);
+  const T y1 = X[0][1] + __shfl_up(X[1][1], TX, 64);
+  val = y0 + carry;
+  ncarry = y1;
+}
+
+// One TX x TY marching tile (bx, by) and z-chunk bz of a 3D Q1 level (the body of k_q1_3d; the
+// batched solver runs it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.
+// STORED (block operator): read c_phi JxW per Gauss point from cp.qcb; otherwise form it from U.
+template <typename T, int MODE, int TX, int TY, bool CHEB, bool STORED = true>
+__device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, int by, int bz, const T* __restrict__ x,
+                                         const T* __restrict__ U, const T* __restrict__ phit,
+                                         const uint8_t* __restrict__ mask, T* __restrict__ y, const ChebFuse<T>& cf) {
+  static_assert(TX * TY == 64, "one wavefront per tile");
+  static_assert(!CHEB || MODE == MODE_BLOCK, "the fused Chebyshev step follows the block operator");
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int lane = threadIdx.x;
+  const int i = lane % TX, j = lane / TX;
+  const int cx = bx * (TX - 1) - 1 + i;
+  const int cy = by * (TY - 1) - 1 + j;
+  const int z_lo = bz * zc;
+  const int z_hi = min(z_lo + zc, cp.nn[2]);
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  const bool own_xy = i >= 1 && j >= 1 && cx <= cp.nn[0] - 1 && cy <= cp.nn[1] - 1;
+  const bool cell_xy = cx >= 0 && cx < cp.N[0] && cy >= 0 && cy < cp.N[1] &&
+                       !cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1]);
+  const Consts<T> kc(cp, 8);
+  const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
+  T carry[4] = {T(0), T(0), T(0), T(0)};
+  for (int kz = z_lo - 1; kz < z_hi; ++kz) {
+    const bool cell = cell_xy && kz >= 0 && kz < cp.N[2];
+    const int64_t g0 = cell ? (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz : 0;
+    int64_t gi[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * sy + (a >> 2) * sz;
+    uint8_t mk[8];
+    T du[3][8];
+    T outu[3][8];
+    if (cell) {
+      T pt[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        mk[a] = mask[gi[a]];
+        pt[a] = phit[gi[a]];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T v = x[c * nn + gi[a]];
+          du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+        }
+      }
+      cell3_u<T>(kc, du, pt, outu);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
+    }
+    T val[4], nc[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) combine3<T, TX>(outu[c], carry[c], val[c], nc[c]);
+    T outp[8];
+    if (cell) {
+      if constexpr (MODE == MODE_BLOCK && STORED) {
+        T dp[8], cq[8];
+        const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)kz * cp.N[0] * cp.N[1];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const T v = x[3 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          cq[a] = qcb[a * cp.n_cells + cid];
+        }
+        cell3_phi_stored<T>(kc, dp, cq, outp);
+      } else {
+        T dp[8], uu[3][8], ph[8];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          const T v = x[3 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) uu[c][a] = U[c * nn + gi[a]];
+          ph[a] = COUPLE ? U[3 * nn + gi[a]] : T(0);
+        }
+        cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) outp[a] = T(0);
+    }
+    combine3<T, TX>(outp, carry[3], val[3], nc[3]);
+    if (own_xy && kz >= z_lo) {
+      const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+      const uint8_t m = mask[go];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int64_t o = c * nn + go;
+        const bool con = m & mask_bit(c, 3);
+        if constexpr (CHEB) {
+          const T c1 = c == 3 ? cf.c1p : cf.c1u, c2 = c == 3 ? cf.c2p : cf.c2u;
+          const T d = x[o];
+          const T r = cf.res[o] - (con ? d : val[c]);
+          cf.res[o] = r;
+          const T dn = c1 * d + c2 * r / cf.diag[o];
+          const T xn = cf.x[o] + dn;
+          cf.x[o] = xn;
+          if (cf.d_out) cf.d_out[o] = dn;
+          if (cf.t_next) cf.t_next[o] = con ? (cf.next_of_x ? xn : dn) : T(0);
+        } else {
+          y[o] = con ? x[o] : val[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) carry[c] = nc[c];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void combine2(const T out[4], T carry, T& val, T& ncarry) {
+  const T x0 = out[0] + __shfl_up(out[1], 1, 64);
+  const T x1 = out[2] + __shfl_up(out[3], 1, 64);
+  val = x0 + carry;
+  ncarry = x1;
+}
+
+// One 64-cell row tile bx and y-chunk by of a 2D Q1 level (the body of k_q1_2d; the batched
+// solver runs it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.
+// STORED as for q1_tile3.
+template <typename T, int MODE, bool STORED = true>
+__device__ __forceinline__ void q1_tile2(const CellParams& cp, int zc, int bx, int by, const T* __restrict__ x,
+                                         const T* __restrict__ U, const T* __restrict__ phit,
+                                         const uint8_t* __restrict__ mask, T* __restrict__ y) {
+  constexpr bool COUPLE = (MODE == MODE_APPLY);
+  const int i = threadIdx.x;
+  const int cx = bx * 63 - 1 + i;
+  const int y_lo = by * zc;
+  const int y_hi = min(y_lo + zc, cp.nn[1]);
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1];
+  const bool own_x = i >= 1 && cx <= cp.nn[0] - 1;
+  const bool cell_x = cx >= 0 && cx < cp.N[0];
+  const Consts<T> kc(cp, 4);
+  const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
+  T carry[3] = {T(0), T(0), T(0)};
+  for (int ky = y_lo - 1; ky < y_hi; ++ky) {
+    const bool cell = cell_x && ky >= 0 && ky < cp.N[1] && !cell_in_hole(cp.lshape, cx, ky, cp.N[0], cp.N[1]);
+    const int64_t g0 = cell ? (int64_t)cx + (int64_t)ky * sy : 0;
+    int64_t gi[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gi[a] = g0 + (a & 1) + (a >> 1) * sy;
+    uint8_t mk[4];
+    T du[2][4], outu[2][4];
+    if (cell) {
+      T pt[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        mk[a] = mask[gi[a]];
+        pt[a] = phit[gi[a]];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const T v = x[c * nn + gi[a]];
+          du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
+        }
+      }
+      cell2_u<T>(kc, du, pt, outu);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) outu[c][a] = T(0);
+    }
+    T val[3], nc[3];
+    combine2<T>(outu[0], carry[0], val[0], nc[0]);
+    combine2<T>(outu[1], carry[1], val[1], nc[1]);
+    T outp[4];
+    if (cell) {
+      if constexpr (MODE == MODE_BLOCK && STORED) {
+        T dp[4], cq[4];
+        const int64_t cid = (int64_t)cx + (int64_t)ky * cp.N[0];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const T v = x[2 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          cq[a] = qcb[a * cp.n_cells + cid];
+        }
+        cell2_phi_stored<T>(kc, dp, cq, outp);
+      } else {
+        T dp[4], uu[2][4], ph[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const T v = x[2 * nn + gi[a]];
+          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
+          uu[0][a] = U[gi[a]];
+          uu[1][a] = U[nn + gi[a]];
+          ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+        }
+        cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 4; ++a) outp[a] = T(0);
+    }
+    combine2<T>(outp, carry[2], val[2], nc[2]);
+    if (own_x && ky >= y_lo) {
+      const int64_t go = (int64_t)cx + (int64_t)ky * sy;
+      const uint8_t m = mask[go];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t o = c * nn + go;
+        y[o] = (m & mask_bit(c, 2)) ? x[o] : val[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+  }
+}
+
+}  // namespace pff

@@ -124,6 +124,9 @@ SIGNATURES = {
     "pf_batch_set_eig_bounds": (I, [VP, I, I, C.POINTER(D)]),
     "pf_batch_set_vcycle_precision": (I, [VP, I]),
     "pf_batch_set_graphs": (I, [VP, I]),
+    "pf_batch_autotune": (I, [VP, I, VP]),
+    "pf_batch_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I), C.POINTER(D)]),
+    "pf_batch_set_tuning": (I, [VP, I, I, I, I, I]),
     "pf_batch_newton_step": (I, [VP, VP, VP, VP, C.POINTER(NewtonReport), VP]),
     "pf_batch_destroy": (None, [VP]),
     "pf_destroy": (None, [VP]),
@@ -583,6 +586,10 @@ def solver_from_spec(s, device="cuda", **opt_overrides):
     return Solver(mesh, s["material"], opt, device)
 
 
+# candidates of pf_batch_autotune, in its order: (shape, zc)
+BATCH_CANDIDATES = [(-1, 0), (2, 0), (0, 4), (0, 8), (0, 16), (0, 32), (1, 4), (1, 8), (1, 16)]
+
+
 class BatchSolver:
     """A batch context (pf_batch_*) with its torch-allocated workspace and packed-layout helpers."""
 
@@ -683,6 +690,28 @@ class BatchSolver:
 
     def set_graphs(self, enable):
         _check(lib().pf_batch_set_graphs(self.b, 1 if enable else 0), "pf_batch_set_graphs")
+
+    def autotune(self, reps=10):
+        """pf_batch_autotune; returns the choices per level: {"level", "choices": [{prec, mode,
+        shape, zc, us}]} with the candidates' times in the order of BATCH_CANDIDATES."""
+        _check(lib().pf_batch_autotune(self.b, reps, _stream()), "pf_batch_autotune")
+        return self.tuning()
+
+    def tuning(self):
+        out = []
+        for l in range(self.L):
+            ch = []
+            for prec, pn in ((PF_F64, "f64"), (PF_F32, "f32")):
+                for mode, mn in ((0, "jacobian"), (1, "block")):
+                    sh, zc, us = I(0), I(0), (D * len(BATCH_CANDIDATES))()
+                    _check(lib().pf_batch_get_tuning(self.b, l, prec, mode, C.byref(sh), C.byref(zc), us),
+                           "pf_batch_get_tuning")
+                    ch.append({"prec": pn, "mode": mn, "shape": sh.value, "zc": zc.value, "us": list(us)})
+            out.append({"level": l, "choices": ch})
+        return out
+
+    def set_tuning(self, level, prec, mode, shape, zc):
+        _check(lib().pf_batch_set_tuning(self.b, level % self.L, prec, mode, shape, zc), "pf_batch_set_tuning")
 
     def newton_step(self, U, Uold, phit, raise_on_error=True):
         reps = (NewtonReport * self.n)()

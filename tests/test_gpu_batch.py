@@ -134,6 +134,66 @@ def test_batch_vcycle_matches_oracle(dim):
             assert e <= 1e-11 and e32 <= 1e-4
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_work_table_shapes(dim):
+    """Every shape of the batched Q1 cell loop (grid-stride over all cells, 64-cell work items with
+    atomic scatter, marching-tile work items with full and ragged chunks), forced on every level for
+    both operators: the apply matches the oracle per instance and level (1e-12 FP64, 2e-6 FP32) and
+    the V-cycle, whose smoother applies B~ through the same shape, matches the oracle's V-cycle with
+    the oracle's smoother intervals (1e-11 FP64 levels, 1e-4 FP32 levels).  Then the autotuner's
+    choice is one of the timed candidates and keeps the same results."""
+    from paper_1902_08112_amd import PF_F32, PF_F64, pff
+    torch = __import__("torch")
+    specs = small_batch(dim, seed=8)
+    print(f"[case] batch work-table shapes dim={dim} n={len(specs)}", flush=True)
+    BS = batch_solver(specs)
+    Us, pts, acts, Hs = [], [], [], []
+    for b, s in enumerate(specs):
+        U, phit = W.random_linearization(s, 170 + b)
+        act = W.random_active(s, 180 + b, 0.1)
+        H = oracle_hierarchy(s)
+        H.set_linearization(U, phit, act)
+        Us.append(U), pts.append(phit), acts.append(act), Hs.append(H)
+    BS.set_linearization(BS.pack(Us), BS.pack(pts, nodes=True), BS.pack(acts, nodes=True))
+    for b in range(len(specs)):
+        inject_batch_bounds(BS, b, Hs[b])
+    rs = [np.random.default_rng(190 + b).uniform(-1, 1, u.size) for b, u in enumerate(Us)]
+    z_ref = [Hs[b].vcycle(rs[b]) for b in range(len(specs))]
+    xs = [[np.random.default_rng(200 + b + 7 * l).uniform(-1, 1, Hs[b].levels[l].n_dofs) for b in range(len(specs))]
+          for l in range(BS.L)]
+
+    def check(tag):
+        for l in range(BS.L):
+            ys = BS.unpack(BS.jacobian_apply(l, BS.pack(xs[l], level=l)), level=l)
+            ys32 = BS.unpack(BS.jacobian_apply(l, BS.pack(xs[l], level=l).to(torch.float32)), level=l)
+            for b in range(len(specs)):
+                ref = Hs[b].mg[l].G @ xs[l][b]
+                e, e32 = rel_err(ys[b], ref), rel_err(ys32[b].astype(np.float64), ref)
+                assert e <= 1e-12 and e32 <= 2e-6, (tag, l, b, e, e32)
+        zs = BS.unpack(BS.vcycle(BS.pack(rs), PF_F64))
+        zs32 = BS.unpack(BS.vcycle(BS.pack(rs), PF_F32))
+        worst = max(rel_err(zs[b], z_ref[b]) for b in range(len(specs)))
+        worst32 = max(rel_err(zs32[b], z_ref[b]) for b in range(len(specs)))
+        print(f"  {tag}: V-cycle worst rel {worst:.2e}, FP32 levels {worst32:.2e}", flush=True)
+        assert worst <= 1e-11 and worst32 <= 1e-4
+
+    shapes = [(-1, 0), (2, 0), (0, 5), (0, 8)] + ([(1, 4), (1, 6)] if dim == 3 else [])
+    for shape, zc in shapes:
+        for l in range(BS.L):
+            for prec in (PF_F64, PF_F32):
+                for mode in (0, 1):
+                    BS.set_tuning(l, prec, mode, shape, zc)
+        check(f"shape {shape} zc {zc}")
+    rep = BS.autotune(reps=3)
+    for lv in rep:
+        for ch in lv["choices"]:
+            timed = [u for u in ch["us"] if u > 0]
+            assert len(timed) >= 6
+            k = pff.BATCH_CANDIDATES.index((ch["shape"], ch["zc"]))
+            assert ch["us"][k] > 0 and ch["us"][k] <= min(timed) * 1.03 + 1e-9
+    check("autotuned")
+
+
 def check_batch_newton_vs_oracle(specs, states, Ub, reps, insts, prec):
     """Batched Newton updates of the given instances against the oracle's Newton step."""
     for b in insts:
