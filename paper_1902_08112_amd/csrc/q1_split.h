@@ -11,6 +11,14 @@
 // Displacement rows: tau = C e(du) - (1 - g(phi~)) C^+ e(du), C^+ h = lam H(tr e) tr h I
 // + 2 mu N (F o (N^T h N)) N^T.  Phase-field rows: E_s^+ and sigma^+ : e(du) from the
 // eigenvalues, sigma^+ : h = lam <tr e>_+ tr h + 2 mu sum_i <lam_i>_+ n_i . h n_i.
+//
+// Since C h = lam tr h I + 2 mu N (1 o (N^T h N)) N^T for the orthonormal N, the displacement
+// tangent is formed as one spectral sum with the weights g F + (1 - F) and g H + (1 - H),
+// each in [g, 1]: no difference of two O(|C|) terms.  Written as C h - (1 - g) C^+ h, a fully
+// broken point in tension (g = kappa, F = H = 1) is kappa |C h| left over from cancelling
+// terms, which FP32 rounding (1e-7 |C h|) swamps: the FP32 operator's rows there turn
+// indefinite, 100-1000 times the true diagonal, and the Chebyshev smoother, whose interval
+// comes from the FP64 operator, amplifies them without bound.
 #pragma once
 
 #include "common.h"
@@ -140,9 +148,10 @@ __host__ __device__ __forceinline__ T tdd(T a, T b) {
   return (tpos(a) - tpos(b)) / (a - b);
 }
 
-// tau = C h - omg C^+ h for the symmetric increment h (of the displacement direction)
+// tau = C h - (1 - g) C^+ h for the symmetric increment h (of the displacement direction), as
+// lam w(H) tr h I + 2 mu N (w(F) o (N^T h N)) N^T with w(f) = g f + (1 - f)
 template <int D, typename T>
-__host__ __device__ __forceinline__ void split_stress(T mu, T lam, T omg, const T* v, const T (&h)[D][D],
+__host__ __device__ __forceinline__ void split_stress(T mu, T lam, T g, const T* v, const T (&h)[D][D],
                                                       T (&tau)[D][D]) {
   using Lt = Layout<D>;
   T N[D][D];
@@ -169,7 +178,7 @@ __host__ __device__ __forceinline__ void split_stress(T mu, T lam, T omg, const 
 #pragma unroll
       for (int i = 0; i < D; ++i) x += N[i][a] * hN[i][b];
       const T f = a == b ? theav(l[a]) : tdd(l[a], l[b]);
-      M[a][b] = f * x;
+      M[a][b] = (g * f + (T(1) - f)) * x;
       M[b][a] = M[a][b];
     }
 #pragma unroll
@@ -184,7 +193,8 @@ __host__ __device__ __forceinline__ void split_stress(T mu, T lam, T omg, const 
   T trh = T(0);
 #pragma unroll
   for (int i = 0; i < D; ++i) trh += h[i][i];
-  const T ltp = lam * theav(tre) * trh;
+  const T ht = theav(tre);
+  const T ltp = lam * (g * ht + (T(1) - ht)) * trh;
 #pragma unroll
   for (int i = 0; i < D; ++i)
 #pragma unroll
@@ -192,9 +202,7 @@ __host__ __device__ __forceinline__ void split_stress(T mu, T lam, T omg, const 
       T x = T(0);
 #pragma unroll
       for (int b = 0; b < D; ++b) x += hN[i][b] * N[j][b];
-      const T cp = T(2) * mu * x + (i == j ? ltp : T(0));          // C^+ h
-      const T c = T(2) * mu * h[i][j] + (i == j ? lam * trh : T(0));  // C h
-      tau[i][j] = c - omg * cp;
+      tau[i][j] = T(2) * mu * x + (i == j ? ltp : T(0));
       tau[j][i] = tau[i][j];
     }
 }
@@ -304,9 +312,9 @@ __host__ __device__ __forceinline__ void cell3_u(const CK<T>& k, const T (&du)[3
       for (int j = 0; j < 3; ++j) h[i][j] = T(0.5) * (G[i][j][rj[j]] + G[j][i][rj[i]]);
     T v[Layout<3>::NV];
     load_record<3, T>(rb, stride, q, v, true);
-    const T omg = (T(1) - k.kap) * (T(1) - pq[q] * pq[q]);  // 1 - g(phi~)
+    const T gq = k.kap + (T(1) - k.kap) * pq[q] * pq[q];  // g(phi~)
     T tau[3][3];
-    split_stress<3, T>(k.mu, k.lam, omg, v, h, tau);
+    split_stress<3, T>(k.mu, k.lam, gq, v, h, tau);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -389,9 +397,9 @@ __host__ __device__ __forceinline__ void cell2_u(const CK<T>& k, const T (&du)[2
       for (int j = 0; j < 2; ++j) h[i][j] = T(0.5) * (G[i][j][rj[j]] + G[j][i][rj[i]]);
     T v[Layout<2>::NV];
     load_record<2, T>(rb, stride, q, v, true);
-    const T omg = (T(1) - k.kap) * (T(1) - pq[q] * pq[q]);
+    const T gq = k.kap + (T(1) - k.kap) * pq[q] * pq[q];  // g(phi~)
     T tau[2][2];
-    split_stress<2, T>(k.mu, k.lam, omg, v, h, tau);
+    split_stress<2, T>(k.mu, k.lam, gq, v, h, tau);
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll

@@ -81,6 +81,61 @@ def test_split_apply_every_shape(name):
             assert e <= 1e-12 and eb <= 1e-12 and e32 <= 2e-6 and eb32 <= 2e-6
 
 
+@pytest.mark.parametrize("name", ["small2d_miehe", "small3d_miehe"])
+def test_split_broken_tension_rows(name):
+    """Every point fully broken (phi~ = 0) and in tension (all principal strains and tr e positive):
+    there C^+ = C and sigma^+ = sigma, so the split operator equals the unsplit one, whose
+    displacement rows are kappa C, ten orders below an undamaged row (Sec. 2.1).  The reference is
+    the unsplit oracle's assembled Jacobian, which forms g C directly.  Written as
+    C - (1 - g) C^+, the displacement tangent there would be a difference of two O(|C|) terms that
+    FP32 rounding swamps; the record-streaming kernels form it as one spectral sum with weights
+    g F + (1 - F), so both record shapes, both operators and both precisions meet the usual bars
+    on the unconstrained displacement rows alone (the constrained rows return x and would hide
+    them).  The split oracle itself, which forms C - (1 - g) C^+ in FP64, is printed for
+    comparison: its cancellation leaves about 1e-6 on these rows."""
+    from paper_1902_08112_amd import pff
+    torch = __import__("torch")
+    s = W.config(name)
+    d = s["dim"]
+    print(f"[case] split broken tension {name}", flush=True)
+    _, X = W.lattice(s)
+    nn = X.shape[0]
+    rng = np.random.default_rng(5)
+    U = np.zeros((d + 1) * nn)
+    for c in range(d):
+        # principal strains about 1e-3 (1, 1.1, 1.2); the perturbation keeps them positive and distinct
+        U[c * nn:(c + 1) * nn] = 1e-3 * (1 + 0.1 * c) * X[:, c] + 1e-7 * rng.uniform(-1, 1, nn)
+    U[d * nn:] = rng.uniform(0, 1, nn)
+    phit = np.zeros(nn)
+    act = np.zeros(nn, dtype=np.uint8)
+    H = oracle_hierarchy(s)
+    H.set_linearization(U, phit, act, eig_bounds=[EIG_DUMMY] * s["n_levels"])
+    plain = model.Material(**dict(s["material"], split="none"))
+    mg_f = H.mg[-1]
+    G0 = model.constrain_matrix(model.assemble_jacobian(H.fine, plain, mg_f.U, mg_f.phit), mg_f.constrained)
+    S = gpu_solver(s)
+    S.set_linearization(dev(U), dev(phit), dev(act))
+    L = s["n_levels"] - 1
+    x = np.random.default_rng(7).uniform(-1, 1, H.fine.n_dofs)
+    ref = G0 @ x
+    rows = np.flatnonzero(~mg_f.constrained[:d * nn])
+    e_or = rel_err((mg_f.G @ x)[rows], ref[rows])
+    print(f"  {rows.size} free displacement rows, |G x| there {np.linalg.norm(ref[rows]):.1e}; split oracle "
+          f"(C - (1 - g) C^+ in FP64) vs unsplit oracle there: {e_or:.1e}", flush=True)
+    for v in (2, 4):
+        for mode in (0, 1):
+            pff.pf_set_tuning(S.ctx, L, pff.PF_F64, mode, v, -1)
+            pff.pf_set_tuning(S.ctx, L, pff.PF_F32, mode, v, -1)
+        for op, tag in ((S.jacobian_apply, "G"), (S.block_apply, "B")):
+            y = host(op(L, dev(x)))
+            y32 = host(op(L, dev(x).to(torch.float32))).astype(np.float64)
+            e, e32 = rel_err(y[rows], ref[rows]), rel_err(y32[rows], ref[rows])
+            print(f"  shape {v} {tag}: displacement rows FP64 {e:.1e} FP32 {e32:.1e}", flush=True)
+            assert e <= 1e-12 and e32 <= 2e-6
+            if tag == "G":
+                assert rel_err(y, ref) <= 1e-12
+
+
 @pytest.mark.parametrize("name", ["tiny2d_miehe", "tiny3d_q2_miehe", "small3d_miehe", "small_lshape_miehe"])
 def test_split_residual_and_diagonal(name):
     s, U, phit, act, H, S = setup_case(name, seed=11)
