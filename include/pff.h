@@ -376,16 +376,21 @@ pf_status pf_set_tuning(pf_ctx* ctx, int level, int prec, int mode, int variant,
 /* JSON text of the choices and measured candidate times (microseconds per apply). */
 pf_status pf_tuning_report(pf_ctx* ctx, char* buf, size_t len);
 
-/* Graph replay of the V-cycle (default off): the first V-cycle after a change
- * of level data, eigenvalue bounds or tuning is captured into a hipGraph on a
- * private stream and replayed on the caller's stream afterwards (pf_vcycle and
- * the FGMRES of pf_newton_step).  enable = 0 launches every kernel directly.
- * The Chebyshev coefficients are kernel arguments of the capture, so every
- * new linearization re-captures; within one Newton step (a handful of
- * V-cycles) the capture costs more than the replays save, so eager launches
- * are the default.  Callers that run many V-cycles per linearization (or that
- * need the launch sequence fixed) enable it. */
+/* Graph replay of the V-cycle: the first V-cycle after setup (or after a change
+ * of pressure, kernel tuning, smoother fusion or coarse-solve path) is captured
+ * into a hipGraph per precision on a private stream and replayed on the
+ * caller's stream afterwards (pf_vcycle and the FGMRES of pf_newton_step).
+ * Everything a new linearization or new eigenvalue bounds change -- level
+ * data, diagonals, stored coefficients, the Chebyshev coefficients, the dense
+ * coarse matrix -- is read by the kernels from device buffers with fixed
+ * addresses, so one capture serves every later linearization.  enable = 0
+ * launches every kernel directly (also while pf_set_kernel_timing is on).
+ * Replays and direct launches compute the same operations; the atomic
+ * scatters of some cell loops may order sums differently (rounding level).
+ * Calls that overlap on one context race. */
 pf_status pf_set_graphs(pf_ctx* ctx, int enable);
+/* Number of V-cycle captures made by the context so far (both precisions). */
+pf_status pf_get_graph_captures(pf_ctx* ctx, int64_t* n);
 
 /* How the coarsest level's Chebyshev solve (Sec. 3.2.2) runs.  The solve is a fixed
  * polynomial in the level operator, so every mode computes the same linear map:
@@ -396,8 +401,9 @@ pf_status pf_set_graphs(pf_ctx* ctx, int enable);
  *   PF_COARSE_FUSED all sweeps in one single-workgroup launch (Q1 levels up to 4096 DoFs),
  *                   else as PF_COARSE_STEPS;
  *   PF_COARSE_STEPS one launch per operator apply and Chebyshev step.
- * After a change to AUTO, or after pf_set_pressure or new level-0 eigenvalue bounds, the
- * fused kernel serves until the next pf_set_linearization rebuilds the matrix. */
+ * New level-0 eigenvalue bounds rebuild the matrix on the stream of the next V-cycle; after
+ * a change to AUTO or after pf_set_pressure the fused kernel serves until the next
+ * pf_set_linearization rebuilds it. */
 #define PF_COARSE_AUTO 0
 #define PF_COARSE_FUSED 1
 #define PF_COARSE_STEPS 2

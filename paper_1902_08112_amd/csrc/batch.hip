@@ -236,7 +236,7 @@ static int64_t b_items_of(const CellParams& cp, int d, int shape, int zc) {
     const int tx = shape == kBShapeMarch16 ? 16 : 8, ty = 64 / tx;
     return (int64_t)((cp.nn[0] + tx - 2) / (tx - 1)) * ((cp.nn[1] + ty - 2) / (ty - 1)) * ((cp.nn[2] + zc - 1) / zc);
   }
-  return (int64_t)((cp.nn[0] + 62) / 63) * ((cp.nn[1] + zc - 1) / zc);
+  return (int64_t)q1_tiles2(cp.nn[0]) * ((cp.nn[1] + zc - 1) / zc);
 }
 
 template <int D, typename T, int SHAPE>

@@ -489,7 +489,7 @@ pf_status launch_block_coef(const Geom& g, const CellParams& cp, const double* U
 // 5 = LDS-staged marching slabs of 16x16 cells (cell_q1_slab.hip; 3D, 2D maps it to 0).
 // q1_set_tile forces a variant / z-chunk (tuning and tests); -1 restores the heuristic.
 static int64_t q1_tiles_xy(const Geom& g, int tile) {
-  if (g.d == 2) return (g.nn[0] + 62) / 63;
+  if (g.d == 2) return q1_tiles2(g.nn[0]);
   const int tx = tile == 1 ? 16 : 8, ty = 64 / tx;
   return (int64_t)((g.nn[0] + tx - 2) / (tx - 1)) * ((g.nn[1] + ty - 2) / (ty - 1));
 }
@@ -597,7 +597,7 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
         k_q1_3d<T, MODE_BLOCK, 8, 8><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, nzc, x, U, phit, mask, y);
     }
   } else {
-    const int64_t ntx = (g.nn[0] + 62) / 63;
+    const int64_t ntx = q1_tiles2(g.nn[0]);
     const int zc = q1_chunk(g, 0, cp.zc);
     dim3 grid((unsigned)ntx, (unsigned)((g.nn[1] + zc - 1) / zc), 1);
     if (mode == MODE_APPLY)

@@ -261,6 +261,12 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   __shared__ uint8_t sm[3][kSMaskPad];
   __shared__ T sx[2][kSWaves - 1][kSX][8];  // cross-wave y exchange (double-buffered by layer parity)
 
+  // the fused step's coefficients, read once (device memory: captured launches follow new bounds)
+  T cc[4] = {T(0), T(0), T(0), T(0)};
+  if constexpr (CHEB) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cc[k] = (T)cf.dc[k];
+  }
   const int64_t t = xcd_tile_s(blockIdx.x, gridDim.x);
   const int bz = (int)(t % nzc);
   const int bx = (int)((t / nzc) % ntx);
@@ -455,7 +461,7 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
         const int64_t o = c * nn + go;
         const bool con = m & mask_bit(c, 3);
         if constexpr (CHEB) {
-          const T c1 = c == 3 ? cf.c1p : cf.c1u, c2 = c == 3 ? cf.c2p : cf.c2u;
+          const T c1 = c == 3 ? cc[2] : cc[0], c2 = c == 3 ? cc[3] : cc[1];
           const T d = xo[c];
           const T r = cf.res[o] - (con ? d : val);
           cf.res[o] = r;

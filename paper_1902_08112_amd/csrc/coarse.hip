@@ -19,11 +19,6 @@ constexpr int kCoarseThreads = 512;
 constexpr int kCoarseMaxDegree = 64;
 constexpr int64_t kCoarseMaxDofs = 4096;  // two LDS vectors of doubles: 64 KiB
 
-struct CoarseCoef {
-  int degree, sweeps;
-  double c1[2][kCoarseMaxDegree], c2[2][kCoarseMaxDegree];  // [block u/phi][step] of the three-term recurrence
-};
-
 // y = Pi_C x + sum over cells of the masked cell operator (full G~ if COUPLE, else B~); x, y in LDS
 template <int D, bool COUPLE>
 __device__ void wg_apply(const CellParams& cp, const double* x, double* y, const double* U, const double* phit,
@@ -50,7 +45,8 @@ __device__ void wg_apply(const CellParams& cp, const double* x, double* y, const
 // COLUMNS: workgroup j solves for b = e_j (0 if DoF j is constrained) and writes x to column j of
 // the dense coarse-solve matrix x = S b (column-major, x + j n; r + j n is its scratch).
 template <int D, bool COUPLE, bool COLUMNS>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, CoarseCoef cc, const double* U,
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, const double* __restrict__ dc, int degree,
+                                                                 int sweeps, const double* U,
                                                                  const double* phit, const uint8_t* mask,
                                                                  const double* diag, const double* b, double* x,
                                                                  double* r) {
@@ -68,7 +64,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
   }
   auto bval = [&](int64_t i) -> double { return COLUMNS ? (i == col ? 1.0 : 0.0) : b[i]; };
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0.0;
-  for (int sw = 0; sw < cc.sweeps; ++sw) {
+  // dc[4 k ..] = {c1, c2} of step k for the displacement block, then the phase-field block; the
+  // next step's values are fetched one step ahead, so their latency hides behind an apply
+  double cn[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) cn[q] = dc[q];
+  for (int sw = 0; sw < sweeps; ++sw) {
     if (sw == 0) {
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = bval(i);
     } else {
@@ -77,11 +78,18 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
       wg_apply<D, COUPLE>(cp, vd, vt, U, phit, mask);
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r[i] = bval(i) - vt[i];
     }
-    for (int k = 0; k < cc.degree; ++k) {
+    for (int k = 0; k < degree; ++k) {
+      double cs[4];
+      const int kn = k + 1 < degree ? k + 1 : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cs[q] = cn[q];
+        cn[q] = dc[4 * kn + q];
+      }
       if (k > 0) wg_apply<D, false>(cp, vd, vt, U, phit, mask);
       for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const int blk = i >= nu ? 1 : 0;
-        const double c1 = cc.c1[blk][k], c2 = cc.c2[blk][k];
+        const double c1 = cs[2 * blk], c2 = cs[2 * blk + 1];
         double ri = r[i], dn;
         if (k == 0) {
           dn = c2 * ri / diag[i];
@@ -101,21 +109,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_solve(CellParams cp, 
 // Q1 levels up to kCoarseMaxDofs and degrees up to kCoarseMaxDegree; *handled = false otherwise.
 // couple: sweep residuals with G~ (P_full) or with B~ (P_diag).  columns: build the dense matrix of
 // the solve instead (n workgroups; x and r hold n x n doubles each, b unused).
-pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
-                              const double* c2u, const double* c1p, const double* c2p, const double* U,
-                              const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, bool couple, hipStream_t s, bool* handled, bool columns) {
+pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* dcoef,
+                              const double* U, const double* phit, const uint8_t* mask, const double* diag,
+                              const double* b, double* x, double* r, bool couple, hipStream_t s, bool* handled,
+                              bool columns) {
   *handled = false;
   if (g.p != 1 || degree > kCoarseMaxDegree || degree < 1 || g.n_dofs > kCoarseMaxDofs) return PF_OK;
-  CoarseCoef cc;
-  cc.degree = degree;
-  cc.sweeps = sweeps;
-  for (int k = 0; k < degree; ++k) {
-    cc.c1[0][k] = c1u[k];
-    cc.c2[0][k] = c2u[k];
-    cc.c1[1][k] = c1p[k];
-    cc.c2[1][k] = c2p[k];
-  }
   const size_t lds = 2 * (size_t)g.n_dofs * sizeof(double);
   const unsigned nwg = columns ? (unsigned)g.n_dofs : 1u;
   if (columns) {
@@ -123,22 +122,26 @@ pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, i
     // single solve uses kCoarseThreads to finish one column fast)
     const int bt = 128;
     if (g.d == 2 && couple)
-      k_coarse_solve<2, true, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<2, true, true><<<nwg, bt, lds, s>>>(cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else if (g.d == 2)
-      k_coarse_solve<2, false, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<2, false, true><<<nwg, bt, lds, s>>>(cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else if (couple)
-      k_coarse_solve<3, true, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<3, true, true><<<nwg, bt, lds, s>>>(cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else
-      k_coarse_solve<3, false, true><<<nwg, bt, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<3, false, true><<<nwg, bt, lds, s>>>(cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
   } else {
     if (g.d == 2 && couple)
-      k_coarse_solve<2, true, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<2, true, false><<<1, kCoarseThreads, lds, s>>>(
+          cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else if (g.d == 2)
-      k_coarse_solve<2, false, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<2, false, false><<<1, kCoarseThreads, lds, s>>>(
+          cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else if (couple)
-      k_coarse_solve<3, true, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<3, true, false><<<1, kCoarseThreads, lds, s>>>(
+          cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
     else
-      k_coarse_solve<3, false, false><<<1, kCoarseThreads, lds, s>>>(cp, cc, U, phit, mask, diag, b, x, r);
+      k_coarse_solve<3, false, false><<<1, kCoarseThreads, lds, s>>>(
+          cp, dcoef, degree, sweeps, U, phit, mask, diag, b, x, r);
   }
   PFF_CHECK_LAUNCH();
   *handled = true;

@@ -119,7 +119,7 @@ struct ChebFuse {
   T* x;
   T* d_out;
   T* t_next;
-  T c1u, c2u, c1p, c2p;
+  const double* dc;  // device: {c1, c2} of the displacement block, then of the phase-field block
   int next_of_x;
 };
 // *handled = false when the level's block operator is not a 3D Q1 marching-tile shape
@@ -182,11 +182,14 @@ pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s);
 //   mode 2: res = b - t;   d = c2*Dinv*res;        x += d   (t = G~ x)
 //   mode 3: res as given;  d = c2*Dinv*res;        x += d
 // t_next (may alias t, or nullptr): t_next = Pi_C d (Pi_C x_new if next_of_x), the
-// starting value of the next operator apply
+// starting value of the next operator apply.  dc: device array {c1, c2} of the displacement
+// block then {c1, c2} of the phase-field block
 template <typename T>
-pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int mode, int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b,
-                        hipStream_t s);
+pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double* dc, int mode, int64_t nn,
+                        int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b, hipStream_t s);
+// dst[0..n) = src[0..n) from host memory, in stream order, through kernel arguments (src may be
+// reused as soon as the call returns)
+pf_status vec_put(double* dst, const double* src, int64_t n, hipStream_t s);
 // dots per block: out[0] = sum over u-block of x*y, out[1] over the phi-block (FP64 accumulation)
 pf_status dot_blocks(const double* x, const double* y, int64_t nn, int d, double* d_partials, double* h_out,
                      hipStream_t s);

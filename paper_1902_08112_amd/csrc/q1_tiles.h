@@ -52,6 +52,12 @@ __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, i
                        !cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1]);
   const Consts<T> kc(cp, 8);
   const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
+  // the fused step's coefficients, read once (device memory: captured launches follow new bounds)
+  T cc[4] = {T(0), T(0), T(0), T(0)};
+  if constexpr (CHEB) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cc[k] = (T)cf.dc[k];
+  }
   T carry[4] = {T(0), T(0), T(0), T(0)};
   for (int kz = z_lo - 1; kz < z_hi; ++kz) {
     const bool cell = cell_xy && kz >= 0 && kz < cp.N[2];
@@ -121,7 +127,7 @@ __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, i
         const int64_t o = c * nn + go;
         const bool con = m & mask_bit(c, 3);
         if constexpr (CHEB) {
-          const T c1 = c == 3 ? cf.c1p : cf.c1u, c2 = c == 3 ? cf.c2p : cf.c2u;
+          const T c1 = c == 3 ? cc[2] : cc[0], c2 = c == 3 ? cc[3] : cc[1];
           const T d = x[o];
           const T r = cf.res[o] - (con ? d : val[c]);
           cf.res[o] = r;
@@ -148,44 +154,89 @@ __device__ __forceinline__ void combine2(const T out[4], T carry, T& val, T& nca
   ncarry = x1;
 }
 
-// One 64-cell row tile bx and y-chunk by of a 2D Q1 level (the body of k_q1_2d; the batched
-// solver runs it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.
-// STORED as for q1_tile3.
+// 2D row tiles: lane i of the wavefront holds node column bx * kT2Cells - 1 + i and, for i < 63, the
+// cell to its right; lanes 1..62 own their nodes, lane 0 is the left halo and lane 63 only lends
+// its node values to lane 62.
+constexpr int kT2Cells = 62;
+__host__ __device__ constexpr int64_t q1_tiles2(int nodes_x) { return (nodes_x + kT2Cells - 1) / kT2Cells; }
+
+// One row tile bx and y-chunk by of a 2D Q1 level (the body of k_q1_2d; the batched solver runs
+// it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.  The wavefront
+// marches up the node rows: each lane loads its own node of the next row once (a contiguous
+// 64-node segment per field), takes the right-hand corners from lane i + 1 by a shuffle and the
+// lower row from the registers of the previous step.  STORED as for q1_tile3.
 template <typename T, int MODE, bool STORED = true>
 __device__ __forceinline__ void q1_tile2(const CellParams& cp, int zc, int bx, int by, const T* __restrict__ x,
                                          const T* __restrict__ U, const T* __restrict__ phit,
                                          const uint8_t* __restrict__ mask, T* __restrict__ y) {
   constexpr bool COUPLE = (MODE == MODE_APPLY);
+  constexpr bool SB = MODE == MODE_BLOCK && STORED;  // phase-field rows from stored coefficients
+  constexpr int NU = SB ? 0 : (COUPLE ? 3 : 2);      // U components the cell reads
   const int i = threadIdx.x;
-  const int cx = bx * 63 - 1 + i;
+  const int cx = bx * kT2Cells - 1 + i;
   const int y_lo = by * zc;
   const int y_hi = min(y_lo + zc, cp.nn[1]);
   const int64_t nn = cp.n_nodes, sy = cp.ns[1];
-  const bool own_x = i >= 1 && cx <= cp.nn[0] - 1;
-  const bool cell_x = cx >= 0 && cx < cp.N[0];
+  const bool node_x = cx >= 0 && cx <= cp.nn[0] - 1;
+  const bool own_x = i >= 1 && i <= kT2Cells && node_x;
+  const bool cell_x = i <= kT2Cells && cx >= 0 && cx < cp.N[0];
   const Consts<T> kc(cp, 4);
   const T* __restrict__ qcb = (const T*)cp.qcb;  // block operator: stored c_phi JxW per point
+
+  // a node row's values at this lane's column: mask, phi~, x (u, phi), U (u[, phi]); zero off the lattice
+  struct Row {
+    int m;
+    T p, xv[3], uv[NU > 0 ? NU : 1];
+  };
+  auto load = [&](int ky, Row& r) {
+    const bool in = node_x && ky >= 0 && ky < cp.nn[1];
+    const int64_t g = in ? (int64_t)cx + (int64_t)ky * sy : 0;
+    r.m = in ? (int)mask[g] : 0;
+    r.p = in ? phit[g] : T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r.xv[c] = in ? x[c * nn + g] : T(0);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) r.uv[c] = in ? U[c * nn + g] : T(0);
+  };
+  auto right = [&](const Row& r, Row& n) {
+    n.m = __shfl_down(r.m, 1, 64);
+    n.p = __shfl_down(r.p, 1, 64);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) n.xv[c] = __shfl_down(r.xv[c], 1, 64);
+#pragma unroll
+    for (int c = 0; c < NU; ++c) n.uv[c] = __shfl_down(r.uv[c], 1, 64);
+  };
+  Row lo, lon, hi, hin;
+  load(y_lo - 1, lo);
+  right(lo, lon);
   T carry[3] = {T(0), T(0), T(0)};
   for (int ky = y_lo - 1; ky < y_hi; ++ky) {
+    load(ky + 1, hi);
+    right(hi, hin);
     const bool cell = cell_x && ky >= 0 && ky < cp.N[1] && !cell_in_hole(cp.lshape, cx, ky, cp.N[0], cp.N[1]);
-    const int64_t g0 = cell ? (int64_t)cx + (int64_t)ky * sy : 0;
-    int64_t gi[4];
+    // corners a = 0 (cx, ky), 1 (cx + 1, ky), 2 (cx, ky + 1), 3 (cx + 1, ky + 1)
+    const int ma[4] = {lo.m, lon.m, hi.m, hin.m};
+    const T pt[4] = {lo.p, lon.p, hi.p, hin.p};
+    T du[2][4], outu[2][4], dp[4], ua[NU > 0 ? NU : 1][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) gi[a] = g0 + (a & 1) + (a >> 1) * sy;
-    uint8_t mk[4];
-    T du[2][4], outu[2][4];
+    for (int c = 0; c < 2; ++c) {
+      const T xa[4] = {lo.xv[c], lon.xv[c], hi.xv[c], hin.xv[c]};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) du[c][a] = (ma[a] & (1 << c)) ? T(0) : xa[a];
+    }
+    {
+      const T xa[4] = {lo.xv[2], lon.xv[2], hi.xv[2], hin.xv[2]};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) dp[a] = (ma[a] & kMaskPhi) ? T(0) : xa[a];
+    }
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      ua[c][0] = lo.uv[c];
+      ua[c][1] = lon.uv[c];
+      ua[c][2] = hi.uv[c];
+      ua[c][3] = hin.uv[c];
+    }
     if (cell) {
-      T pt[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        mk[a] = mask[gi[a]];
-        pt[a] = phit[gi[a]];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const T v = x[c * nn + gi[a]];
-          du[c][a] = (mk[a] & (1 << c)) ? T(0) : v;
-        }
-      }
       cell2_u<T>(kc, du, pt, outu);
     } else {
 #pragma unroll
@@ -198,25 +249,19 @@ __device__ __forceinline__ void q1_tile2(const CellParams& cp, int zc, int bx, i
     combine2<T>(outu[1], carry[1], val[1], nc[1]);
     T outp[4];
     if (cell) {
-      if constexpr (MODE == MODE_BLOCK && STORED) {
-        T dp[4], cq[4];
+      if constexpr (SB) {
+        T cq[4];
         const int64_t cid = (int64_t)cx + (int64_t)ky * cp.N[0];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const T v = x[2 * nn + gi[a]];
-          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
-          cq[a] = qcb[a * cp.n_cells + cid];
-        }
+        for (int a = 0; a < 4; ++a) cq[a] = qcb[a * cp.n_cells + cid];
         cell2_phi_stored<T>(kc, dp, cq, outp);
       } else {
-        T dp[4], uu[2][4], ph[4];
+        T uu[2][4], ph[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          const T v = x[2 * nn + gi[a]];
-          dp[a] = (mk[a] & kMaskPhi) ? T(0) : v;
-          uu[0][a] = U[gi[a]];
-          uu[1][a] = U[nn + gi[a]];
-          ph[a] = COUPLE ? U[2 * nn + gi[a]] : T(0);
+          uu[0][a] = ua[0][a];
+          uu[1][a] = ua[NU > 1 ? 1 : 0][a];
+          ph[a] = COUPLE ? ua[NU > 2 ? 2 : 0][a] : T(0);
         }
         cell2_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
       }
@@ -227,15 +272,13 @@ __device__ __forceinline__ void q1_tile2(const CellParams& cp, int zc, int bx, i
     combine2<T>(outp, carry[2], val[2], nc[2]);
     if (own_x && ky >= y_lo) {
       const int64_t go = (int64_t)cx + (int64_t)ky * sy;
-      const uint8_t m = mask[go];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int64_t o = c * nn + go;
-        y[o] = (m & mask_bit(c, 2)) ? x[o] : val[c];
-      }
+      for (int c = 0; c < 3; ++c) y[c * nn + go] = (lo.m & mask_bit(c, 2)) ? lo.xv[c] : val[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) carry[c] = nc[c];
+    lo = hi;
+    lon = hin;
   }
 }
 

@@ -39,10 +39,9 @@ pf_status quantity_energies_noalloc(const Geom& gm, const CellParams& cp, double
                                     int device, double* d_out, hipStream_t s);
 pf_status quantity_face_traction(const Geom& gm, const CellParams& cp, int face, const double* U, double* d_part,
                                  double* out, hipStream_t s);
-pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* c1u,
-                              const double* c2u, const double* c1p, const double* c2p, const double* U,
-                              const double* phit, const uint8_t* mask, const double* diag, const double* b,
-                              double* x, double* r, bool couple, hipStream_t s, bool* handled,
+pf_status launch_coarse_solve(const Geom& g, const CellParams& cp, int degree, int sweeps, const double* dcoef,
+                              const double* U, const double* phit, const uint8_t* mask, const double* diag,
+                              const double* b, double* x, double* r, bool couple, hipStream_t s, bool* handled,
                               bool columns = false);
 pf_status coarse_matvec(const double* S, const double* b, double* x, int64_t n, hipStream_t s);
 pf_status coarse_transpose(const double* C, double* T, int64_t n, hipStream_t s);
@@ -203,9 +202,15 @@ struct pf_ctx {
   double *V = nullptr, *Z = nullptr;
   double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
   EigDev* eigdev = nullptr;  // one record per level
-  // captured V-cycles per precision (input vin, output vout); invalid after any change of
-  // level data, eigenvalue bounds or kernel tuning
-  double *vin = nullptr, *vout = nullptr;
+  // Chebyshev coefficients in device memory, 4 per step ({c1, c2} of the displacement block, then of
+  // the phase-field block): the smoother of each level (cheb_degree steps), then the coarse solve
+  // (coarse_degree steps), then one step of the autotuner's timing runs.  Kernels read them there,
+  // so a captured V-cycle stays valid when the eigenvalue bounds change.
+  double* dcoef = nullptr;
+  bool coef_stale = true;    // host bounds changed since the last upload
+  bool dense_stale = false;  // level-0 bounds changed: the dense coarse matrix is rebuilt before the next V-cycle
+  // captured V-cycles per precision (finest-level vb -> vx); invalid after any change of
+  // operator parameters, kernel tuning or the path of the coarse solve
   hipStream_t cap_stream = nullptr;
   // per-level helper streams of the linearization set-up (diagonals and eigenvalue CGs of
   // all levels run concurrently), their join events, and per-level reduction scratch
@@ -227,7 +232,8 @@ struct pf_ctx {
   hipGraph_t vgraph[2] = {nullptr, nullptr};
   hipGraphExec_t vexec[2] = {nullptr, nullptr};
   bool vvalid[2] = {false, false};
-  bool use_graphs = false;  // eager launches: a capture per linearization costs more than replays save
+  bool use_graphs = false;
+  int64_t n_captures = 0;
   // coarse solve: PF_COARSE_AUTO = the dense matrix of the fixed Chebyshev solve (small Q1 coarse
   // levels, built once per linearization) else the single-workgroup kernel; PF_COARSE_FUSED;
   // PF_COARSE_STEPS = one launch per operator apply and vector step
@@ -458,8 +464,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   EigDev* eigdev = cv.take<EigDev>(L);
   double* part_lev = cv.take<double>((size_t)L * kPartStride);
   double* qpart = cv.take<double>(3 * 1024 + 64);
-  double* vin = cv.take<double>(nd);
-  double* vout = cv.take<double>(nd);
+  double* dcoef = cv.take<double>(4 * ((size_t)L * o.cheb_degree + o.coarse_degree + 1));
   double *Sc = nullptr, *Rc = nullptr;
   if (dense_coarse_eligible(lev[0].g, o)) {
     const size_t n0 = (size_t)lev[0].g.n_dofs;
@@ -485,8 +490,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->eigdev = eigdev;
     c->part_lev = part_lev;
     c->qpart = qpart;
-    c->vin = vin;
-    c->vout = vout;
+    c->dcoef = dcoef;
     c->Sc = Sc;
     c->Rc = Rc;
   }
@@ -575,15 +579,55 @@ ChebCoef cheb_coefs(double lo, double hi, int degree) {
   return r;
 }
 
+// the device coefficient blocks (pf_ctx::dcoef)
+double* smooth_coefs(pf_ctx* c, int l) { return c->dcoef + (size_t)4 * l * c->opt.cheb_degree; }
+double* coarse_coefs(pf_ctx* c) { return smooth_coefs(c, (int)c->lev.size()); }
+double* tune_coefs(pf_ctx* c) { return coarse_coefs(c) + (size_t)4 * c->opt.coarse_degree; }
+
+// steps of both blocks interleaved as the kernels read them: {c1, c2} (u), {c1, c2} (phi) per step
+std::vector<double> interleave(const ChebCoef& u, const ChebCoef& p) {
+  std::vector<double> h(4 * u.c1.size());
+  for (size_t k = 0; k < u.c1.size(); ++k) {
+    h[4 * k] = u.c1[k];
+    h[4 * k + 1] = u.c2[k];
+    h[4 * k + 2] = p.c1[k];
+    h[4 * k + 3] = p.c2[k];
+  }
+  return h;
+}
+
+// Level l's smoother coefficients for its current bounds -- the interval [lam_max / ratio, lam_max]
+// scaled by the safety factor per block -- and on level 0 those of the coarse solve, whose
+// interval reaches down to a fraction of lam_min (Sec. 3.2.1, 3.2.2); written in stream order.
+pf_status put_level_coefs(pf_ctx* c, int l, hipStream_t s) {
+  const LevelBuf& b = c->lev[l];
+  const pf_options& o = c->opt;
+  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
+  const double lo[2] = {hi[0] / o.cheb_ratio, hi[1] / o.cheb_ratio};
+  std::vector<double> h =
+      interleave(cheb_coefs(lo[0], hi[0], o.cheb_degree), cheb_coefs(lo[1], hi[1], o.cheb_degree));
+  PFF_TRY(vec_put(smooth_coefs(c, l), h.data(), (int64_t)h.size(), s));
+  if (l == 0) {
+    const double clo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
+    h = interleave(cheb_coefs(clo[0], hi[0], o.coarse_degree), cheb_coefs(clo[1], hi[1], o.coarse_degree));
+    PFF_TRY(vec_put(coarse_coefs(c), h.data(), (int64_t)h.size(), s));
+  }
+  return PF_OK;
+}
+pf_status put_all_coefs(pf_ctx* c, hipStream_t s) {
+  for (int l = 0; l < (int)c->lev.size(); ++l) PFF_TRY(put_level_coefs(c, l, s));
+  c->coef_stale = false;
+  return PF_OK;
+}
+
 // x += Cheb_B(r) with per-block intervals, starting from r as selected by first_mode
 // (vec_cheb_step: 1 = b with x = 0, 2 = b - t with t = G~ x, 3 = res as given); res is
 // overwritten; uses vd, vt of the level.  tail_init: the last step leaves t = Pi_C x, the
-// start of a following G~ x apply.
+// start of a following G~ x apply.  dcoef: the degree steps' coefficients in device memory.
 template <typename T>
-pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2], const double hi[2], int degree,
-                   int first_mode, const T* bvec, bool tail_init, hipStream_t s) {
+pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double* dcoef, int degree, int first_mode,
+                   const T* bvec, bool tail_init, hipStream_t s) {
   LevelBuf& b = c->lev[l];
-  const ChebCoef cu = cheb_coefs(lo[0], hi[0], degree), cpz = cheb_coefs(lo[1], hi[1], degree);
   T* dv = (T*)b.vd;
   T* t = (T*)b.vt;
   const T* diag = prec == PF_F64 ? (const T*)b.diag : (const T*)b.diag32;
@@ -608,10 +652,7 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
       cf.x = x;
       cf.d_out = last ? nullptr : (din == dv ? t : dv);
       cf.t_next = last && tail_init ? t : nullptr;
-      cf.c1u = (T)cu.c1[k];
-      cf.c2u = (T)cu.c2[k];
-      cf.c1p = (T)cpz.c1[k];
-      cf.c2p = (T)cpz.c2[k];
+      cf.dc = dcoef + 4 * k;
       cf.next_of_x = 1;
       bool handled = false;
       const bool timed = ((c->ktime_mask >> 2) & 1) && prec == PF_F64 && l == (int)c->lev.size() - 1 &&
@@ -628,7 +669,6 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
       continue;
     }
     if (k > 0) PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, dv, t, s, fuse));
-    const double c1[2] = {cu.c1[k], cpz.c1[k]}, c2[2] = {cu.c2[k], cpz.c2[k]};
     T* t_next = nullptr;
     int next_of_x = 0;
     if (k + 1 < degree) {
@@ -637,8 +677,8 @@ pf_status cheb_run(pf_ctx* c, int l, int prec, T* res, T* x, const double lo[2],
       t_next = t;
       next_of_x = 1;
     }
-    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, c1, c2, k == 0 ? first_mode : 0, b.g.n_nodes, b.g.d, b.mask,
-                             t_next, next_of_x, bvec, s));
+    PFF_TRY(vec_cheb_step<T>(res, t, dv, x, diag, dcoef + 4 * k, k == 0 ? first_mode : 0, b.g.n_nodes, b.g.d,
+                             b.mask, t_next, next_of_x, bvec, s));
   }
   return PF_OK;
 }
@@ -658,10 +698,7 @@ pf_status smooth(pf_ctx* c, int l, int prec, bool x_zero, bool tail_init, hipStr
   T* x = (T*)b.vx;
   T* r = (T*)b.vr;
   if (!x_zero) PFF_TRY(level_apply(c, l, prec, cycle_mode(c), x, b.vt, s));
-  const pf_options& o = c->opt;
-  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
-  const double lo[2] = {hi[0] / o.cheb_ratio, hi[1] / o.cheb_ratio};
-  return cheb_run<T>(c, l, prec, r, x, lo, hi, o.cheb_degree, x_zero ? 1 : 2, bb, tail_init, s);
+  return cheb_run<T>(c, l, prec, r, x, smooth_coefs(c, l), c->opt.cheb_degree, x_zero ? 1 : 2, bb, tail_init, s);
 }
 
 pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
@@ -670,38 +707,32 @@ pf_status coarse_solve(pf_ctx* c, hipStream_t s) {
   double* x = (double*)b.vx;
   double* r = (double*)b.vr;
   const pf_options& o = c->opt;
-  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
-  const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
   if (c->coarse_mode == PF_COARSE_AUTO && c->coarse_dense_ok) return coarse_matvec(c->Rc, bb, x, b.g.n_dofs, s);
   if (c->coarse_mode != PF_COARSE_STEPS && !c->mat.split) {
-    const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
     bool handled = false;
-    PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
-                                cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, bb, x, r,
-                                cycle_mode(c) == MODE_APPLY, s, &handled));
+    PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, coarse_coefs(c), b.U, b.phit,
+                                b.mask, b.diag, bb, x, r, cycle_mode(c) == MODE_APPLY, s, &handled));
     if (handled) return PF_OK;
   }
   for (int sw = 0; sw < o.coarse_sweeps; ++sw) {
     if (sw > 0) PFF_TRY(level_apply(c, 0, PF_F64, cycle_mode(c), x, b.vt, s));
     // sweep 0 starts from x = 0 (r = b), later sweeps from r = b - G~ x
-    PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, lo, hi, o.coarse_degree, sw == 0 ? 1 : 2, bb, false, s));
+    PFF_TRY(cheb_run<double>(c, 0, PF_F64, r, x, coarse_coefs(c), o.coarse_degree, sw == 0 ? 1 : 2, bb, false, s));
   }
   return PF_OK;
 }
 
-// the dense matrix of the coarse solve for the current level-0 data and lambda bounds
+// the dense matrix of the coarse solve for the current level-0 data and lambda bounds (the
+// coarse coefficients must have been written on stream s)
 pf_status build_coarse_dense(pf_ctx* c, hipStream_t s) {
   c->coarse_dense_ok = false;
   if (!c->Sc || c->coarse_mode != PF_COARSE_AUTO || c->mat.split) return PF_OK;
   LevelBuf& b = c->lev[0];
   const pf_options& o = c->opt;
-  const double hi[2] = {o.cheb_safety * b.eig[1], o.cheb_safety * b.eig[3]};
-  const double lo[2] = {o.coarse_lo_factor * b.eig[0], o.coarse_lo_factor * b.eig[2]};
-  const ChebCoef cu = cheb_coefs(lo[0], hi[0], o.coarse_degree), cp = cheb_coefs(lo[1], hi[1], o.coarse_degree);
   bool handled = false;
-  PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, cu.c1.data(), cu.c2.data(),
-                              cp.c1.data(), cp.c2.data(), b.U, b.phit, b.mask, b.diag, nullptr, c->Sc, c->Rc,
-                              cycle_mode(c) == MODE_APPLY, s, &handled, true));
+  PFF_TRY(launch_coarse_solve(b.g, cparams(c, 0), o.coarse_degree, o.coarse_sweeps, coarse_coefs(c), b.U, b.phit,
+                              b.mask, b.diag, nullptr, c->Sc, c->Rc, cycle_mode(c) == MODE_APPLY, s, &handled,
+                              true));
   if (handled) PFF_TRY(coarse_transpose(c->Sc, c->Rc, b.g.n_dofs, s));
   c->coarse_dense_ok = handled;
   return PF_OK;
@@ -749,29 +780,40 @@ pf_status vcycle_level(pf_ctx* c, int l, int vprec, hipStream_t s) {
   return PF_OK;
 }
 
-pf_status vcycle(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
+// the finest level's right-hand side vb = Pi_F r (in the level's precision), and z = Pi_F vx
+pf_status vcycle_in(pf_ctx* c, int vprec, const double* r, hipStream_t s) {
   const int L = (int)c->lev.size() - 1;
   LevelBuf& f = c->lev[L];
-  const int pl = level_prec(c, L, vprec);
-  if (pl == PF_F64)
-    PFF_TRY(mask_free<double, double>((double*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s));
-  else
-    PFF_TRY(mask_free<double, float>((float*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s));
-  PFF_TRY(vcycle_level(c, L, vprec, s));
-  if (pl == PF_F64)
-    PFF_TRY(mask_free<double, double>(z, (const double*)f.vx, f.mask, f.g.n_nodes, f.g.d, s));
-  else
-    PFF_TRY(mask_free<float, double>(z, (const float*)f.vx, f.mask, f.g.n_nodes, f.g.d, s));
-  return PF_OK;
+  if (level_prec(c, L, vprec) == PF_F64)
+    return mask_free<double, double>((double*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s);
+  return mask_free<double, float>((float*)f.vb, r, f.mask, f.g.n_nodes, f.g.d, s);
+}
+pf_status vcycle_out(pf_ctx* c, int vprec, double* z, hipStream_t s) {
+  const int L = (int)c->lev.size() - 1;
+  LevelBuf& f = c->lev[L];
+  if (level_prec(c, L, vprec) == PF_F64)
+    return mask_free<double, double>(z, (const double*)f.vx, f.mask, f.g.n_nodes, f.g.d, s);
+  return mask_free<float, double>(z, (const float*)f.vx, f.mask, f.g.n_nodes, f.g.d, s);
 }
 
-// The V-cycle has no host decision inside and all its coefficients are fixed
-// until the level data change, so it is captured once into a hipGraph (per
-// precision) on a private stream and replayed on the caller's stream: one
-// launch instead of ~10 per level per smoothing step.
+pf_status vcycle(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
+  PFF_TRY(vcycle_in(c, vprec, r, s));
+  PFF_TRY(vcycle_level(c, (int)c->lev.size() - 1, vprec, s));
+  return vcycle_out(c, vprec, z, s);
+}
+
+// The V-cycle has no host decision inside, and every value that changes with the
+// linearization (level data, diagonals, Chebyshev coefficients, the dense coarse
+// matrix) is read from device buffers that keep their addresses, so it is
+// captured once into a hipGraph (per precision) on a private stream and replayed
+// on the caller's stream across linearizations: one launch instead of ~10 per
+// level per smoothing step.  The capture covers the levels only (finest-level
+// vb -> vx); the masked copies in and out, whose vectors change with every call,
+// run as ordinary launches around the replay.  A new pressure, kernel tuning or
+// coarse-solve path changes kernel arguments or the launch sequence and drops
+// the capture.
 pf_status vcycle_graph(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
   const int k = vprec == PF_F64 ? 0 : 1;
-  const int64_t n = c->lev.back().g.n_dofs;
   if (!c->vvalid[k]) {
     // B~'s per-point coefficients follow a pressure set since the linearization here, on the
     // caller's stream, so that the capture does not record their refresh
@@ -783,7 +825,7 @@ pf_status vcycle_graph(pf_ctx* c, int vprec, const double* r, double* z, hipStre
     c->vexec[k] = nullptr;
     c->vgraph[k] = nullptr;
     PFF_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    const pf_status st = vcycle(c, vprec, c->vin, c->vout, c->cap_stream);
+    const pf_status st = vcycle_level(c, (int)c->lev.size() - 1, vprec, c->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     if (st != PF_OK || e != hipSuccess) {
@@ -794,15 +836,23 @@ pf_status vcycle_graph(pf_ctx* c, int vprec, const double* r, double* z, hipStre
     c->vgraph[k] = g;
     PFF_HIP(hipGraphInstantiate(&c->vexec[k], g, nullptr, nullptr, 0));
     c->vvalid[k] = true;
+    ++c->n_captures;
   }
-  PFF_TRY(vec_copy<double>(c->vin, r, n, s));
+  PFF_TRY(vcycle_in(c, vprec, r, s));
   PFF_HIP(hipGraphLaunch(c->vexec[k], s));
-  PFF_TRY(vec_copy<double>(z, c->vout, n, s));
-  return PF_OK;
+  return vcycle_out(c, vprec, z, s);
 }
 
 pf_status vcycle_any(pf_ctx* c, int vprec, const double* r, double* z, hipStream_t s) {
-  return c->use_graphs ? vcycle_graph(c, vprec, r, z, s) : vcycle(c, vprec, r, z, s);
+  if (c->coef_stale) PFF_TRY(put_all_coefs(c, s));
+  if (c->dense_stale) {
+    // same path, new matrix (in place): a captured V-cycle stays valid
+    PFF_TRY(build_coarse_dense(c, s));
+    c->dense_stale = false;
+    if (!c->coarse_dense_ok) c->drop_graphs();
+  }
+  // kernel timing records events between launches: timed runs launch eagerly
+  return c->use_graphs && !c->ktime_mask ? vcycle_graph(c, vprec, r, z, s) : vcycle(c, vprec, r, z, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -938,19 +988,26 @@ pf_status set_linearization(pf_ctx* c, const double* U, const double* phit, cons
     PFF_HIP(hipEventRecord(c->aux_ev[l], c->aux[l]));
   }
   PFF_TRY(level_task(c, L, s));
+  const bool dense_before = c->coarse_dense_ok;
   if (L > 0) {
     // the dense coarse-solve matrix needs level 0 only: it is built on level 0's stream while
     // the finest level's task (queued above) still runs
     PFF_TRY(eig_readback_level(c, 0, c->aux[0]));
+    PFF_TRY(put_level_coefs(c, 0, c->aux[0]));
     PFF_TRY(build_coarse_dense(c, c->aux[0]));
     PFF_HIP(hipEventRecord(c->aux_ev[0], c->aux[0]));
   }
   for (int l = 0; l < L; ++l) PFF_HIP(hipStreamWaitEvent(s, c->aux_ev[l], 0));
   PFF_TRY(eig_readback(c, s));
+  for (int l = L > 0 ? 1 : 0; l <= L; ++l) PFF_TRY(put_level_coefs(c, l, s));
   if (L == 0) PFF_TRY(build_coarse_dense(c, s));
   PFF_HIP(hipStreamSynchronize(s));
+  c->coef_stale = false;
+  c->dense_stale = false;
   c->has_lin = true;
-  c->drop_graphs();  // the Chebyshev coefficients are kernel arguments of the captured V-cycle
+  // a captured V-cycle reads everything above in place; only a change of the coarse path
+  // (dense matrix or Chebyshev kernel) changes its launch sequence
+  if (c->coarse_dense_ok != dense_before) c->drop_graphs();
   return PF_OK;
 }
 
@@ -1447,8 +1504,10 @@ pf_status pf_set_eig_bounds(pf_ctx* ctx, int level, const double in[4]) {
   }
   for (int k = 0; k < 4; ++k) b.eig[k] = in[k];
   b.eig_fixed = true;
-  ctx->drop_graphs();
-  if (level == 0) ctx->coarse_dense_ok = false;  // the fused kernel serves until the next set-up
+  // written on the stream of the next V-cycle, which also rebuilds the dense coarse matrix for
+  // new level-0 bounds
+  ctx->coef_stale = true;
+  if (level == 0 && ctx->coarse_dense_ok) ctx->dense_stale = true;
   return PF_OK;
 }
 
@@ -1733,7 +1792,9 @@ static pf_status time_cheb_step(pf_ctx* c, int l, int prec, bool fused, int reps
   const T* Ul = prec == PF_F64 ? (const T*)b.U : (const T*)b.U32;
   const T* pl = prec == PF_F64 ? (const T*)b.phit : (const T*)b.phit32;
   const CellParams bcp = level_params(c, l, prec, MODE_BLOCK);
-  const double c1[2] = {0.5, 0.5}, c2[2] = {1e-3, 1e-3};
+  const double hc[4] = {0.5, 1e-3, 0.5, 1e-3};
+  double* dc = tune_coefs(c);
+  PFF_TRY(vec_put(dc, hc, 4, s));
   for (T* v : {d, res, x, dout}) PFF_TRY(vec_fill<T>(v, T(1), nd, s));
   auto step = [&]() -> pf_status {
     if (fused) {
@@ -1743,8 +1804,7 @@ static pf_status time_cheb_step(pf_ctx* c, int l, int prec, bool fused, int reps
       cf.x = x;
       cf.d_out = dout;
       cf.t_next = nullptr;
-      cf.c1u = cf.c1p = T(c1[0]);
-      cf.c2u = cf.c2p = T(c2[0]);
+      cf.dc = dc;
       cf.next_of_x = 0;
       bool handled = false;
       PFF_TRY(launch_q1_block_cheb<T>(b.g, bcp, d, Ul, pl, b.mask, cf, s, &handled));
@@ -1755,7 +1815,7 @@ static pf_status time_cheb_step(pf_ctx* c, int l, int prec, bool fused, int reps
       return PF_OK;
     }
     PFF_TRY(level_apply(c, l, prec, MODE_BLOCK, d, t, s));
-    return vec_cheb_step<T>(res, t, d, x, diag, c1, c2, 0, b.g.n_nodes, b.g.d, b.mask, nullptr, 0, nullptr, s);
+    return vec_cheb_step<T>(res, t, d, x, diag, dc, 0, b.g.n_nodes, b.g.d, b.mask, nullptr, 0, nullptr, s);
   };
   for (int w = 0; w < 2; ++w) PFF_TRY(step());
   PFF_HIP(hipEventRecord(e0, s));
@@ -1951,6 +2011,16 @@ pf_status pf_set_graphs(pf_ctx* ctx, int enable) {
   NEED_CTX();
   ctx->use_graphs = enable != 0;
   if (!ctx->use_graphs) ctx->drop_graphs();
+  return PF_OK;
+}
+
+pf_status pf_get_graph_captures(pf_ctx* ctx, int64_t* n) {
+  NEED_CTX();
+  if (!n) {
+    set_error("n must not be null");
+    return PF_ERR_INVALID_ARG;
+  }
+  *n = ctx->n_captures;
   return PF_OK;
 }
 

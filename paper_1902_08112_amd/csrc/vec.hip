@@ -109,11 +109,15 @@ pf_status vec_sub(T* z, const T* x, const T* y, int64_t n, hipStream_t s) {
 // 1 = b with x = 0 (x is written, not read); 2 = b - t with t = G~ x;
 // 3 = res as given.  t_next, if set, receives Pi_C of the new direction (or of
 // the new x when next_of_x) as the starting value of the next operator apply.
+// dc holds the step's coefficients in device memory, {c1, c2} of the
+// displacement block then of the phase-field block, so that a captured launch
+// stays valid when the eigenvalue bounds change.
 template <typename T>
-__global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1u, T c2u, T c1p, T c2p, int mode,
+__global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double* __restrict__ dc, int mode,
                             int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b) {
   const int64_t n = (int64_t)(d + 1) * nn;
   const int64_t nu = (int64_t)d * nn;
+  const T c1u = (T)dc[0], c2u = (T)dc[1], c1p = (T)dc[2], c2p = (T)dc[3];
   GRID_STRIDE(i, n) {
     const bool phi = i >= nu;
     const T c1 = phi ? c1p : c1u, c2 = phi ? c2p : c2u;
@@ -138,12 +142,31 @@ __global__ void k_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, T c1
   }
 }
 template <typename T>
-pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double c1[2], const double c2[2],
-                        int mode, int64_t nn, int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b,
-                        hipStream_t s) {
-  k_cheb_step<T><<<nblocks((d + 1) * nn), 256, 0, s>>>(res, t, dv, x, diag, (T)c1[0], (T)c2[0], (T)c1[1],
-                                                       (T)c2[1], mode, nn, d, mask, t_next, next_of_x, b);
+pf_status vec_cheb_step(T* res, const T* t, T* dv, T* x, const T* diag, const double* dc, int mode, int64_t nn,
+                        int d, const uint8_t* mask, T* t_next, int next_of_x, const T* b, hipStream_t s) {
+  k_cheb_step<T><<<nblocks((d + 1) * nn), 256, 0, s>>>(res, t, dv, x, diag, dc, mode, nn, d, mask, t_next,
+                                                       next_of_x, b);
   PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
+// Small host arrays (solver coefficients) written into device memory in stream order: the values
+// travel as kernel arguments, so the host copy may change as soon as the call returns.
+constexpr int kPutChunk = 256;
+struct PutChunk {
+  double v[kPutChunk];
+};
+__global__ void k_put(double* dst, PutChunk p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = p.v[i];
+}
+pf_status vec_put(double* dst, const double* src, int64_t n, hipStream_t s) {
+  for (int64_t o = 0; o < n; o += kPutChunk) {
+    const int m = (int)std::min<int64_t>(kPutChunk, n - o);
+    PutChunk p;
+    for (int i = 0; i < m; ++i) p.v[i] = src[o + i];
+    k_put<<<1, 256, 0, s>>>(dst + o, p, m);
+    PFF_CHECK_LAUNCH();
+  }
   return PF_OK;
 }
 
@@ -488,8 +511,8 @@ pf_status eig_cg_beta(T* r, const T* Ap, T* z, T* p, const T* diag, const uint8_
   template pf_status vec_set_constrained<T>(T*, T, const uint8_t*, int64_t, int, hipStream_t);                 \
   template pf_status vec_axpby<T>(T*, T, const T*, T, int64_t, hipStream_t);                                   \
   template pf_status vec_sub<T>(T*, const T*, const T*, int64_t, hipStream_t);                                 \
-  template pf_status vec_cheb_step<T>(T*, const T*, T*, T*, const T*, const double*, const double*, int, int64_t, \
-                                      int, const uint8_t*, T*, int, const T*, hipStream_t);
+  template pf_status vec_cheb_step<T>(T*, const T*, T*, T*, const T*, const double*, int, int64_t, int,          \
+                                      const uint8_t*, T*, int, const T*, hipStream_t);
 INST_T(double)
 INST_T(float)
 #define INST_EIG(T)                                                                                            \

@@ -96,6 +96,7 @@ SIGNATURES = {
     "pf_set_vcycle_precision": (I, [VP, I]),
     "pf_autotune": (I, [VP, I, VP]),
     "pf_set_graphs": (I, [VP, I]),
+    "pf_get_graph_captures": (I, [VP, C.POINTER(C.c_int64)]),
     "pf_set_coarse_mode": (I, [VP, I]),
     "pf_get_tuning": (I, [VP, I, I, I, C.POINTER(I), C.POINTER(I)]),
     "pf_set_tuning": (I, [VP, I, I, I, I, I]),
@@ -509,6 +510,12 @@ class Solver:
 
     def set_graphs(self, enable):
         _check(lib().pf_set_graphs(self.ctx, 1 if enable else 0), "pf_set_graphs")
+
+    def graph_captures(self):
+        """V-cycle captures made by this context so far (pf_get_graph_captures)."""
+        n = C.c_int64(0)
+        _check(lib().pf_get_graph_captures(self.ctx, C.byref(n)), "pf_get_graph_captures")
+        return n.value
 
     def set_coarse_mode(self, mode):
         """PF_COARSE_AUTO (dense matrix of the coarse solve when small), PF_COARSE_FUSED or PF_COARSE_STEPS."""

@@ -381,6 +381,73 @@ def test_vcycle_graph_replay_matches_eager(name):
     assert rel_err(z_eager3, z_eager2) > 1e-9
 
 
+GRAPH_RELIN_CASES = [("small3d", None, 0), ("small3d", (0, 3), 1), ("small3d", (5, 3), 2), ("small_lshape", None, 1),
+                     ("small3d_q2", None, 0), ("cfg1_2d_q1_32", None, 1)]
+
+
+@pytest.mark.parametrize("name,tiles,coarse", GRAPH_RELIN_CASES)
+def test_vcycle_graph_survives_relinearization(name, tiles, coarse):
+    """One capture per precision serves every later linearization and every new eigenvalue bound
+    (the kernels read level data and Chebyshev coefficients from device memory): a solver that
+    replays its captured V-cycles and one that launches eagerly, given the same linearizations
+    (new U, phi~ and active set each time) and injected bounds, agree after each, and the replay
+    after the last one matches the oracle's V-cycle with the oracle's bounds.  A coarse solve whose
+    operator sums cell contributions with atomics in no fixed order (the single-workgroup kernel of
+    coarse mode 1, the Q2 coarse level) has its rounding-level differences amplified by the
+    degree-20 Chebyshev polynomial: two eager launches, like a replay and an eager launch, then
+    agree to about 1e-9 rather than 1e-12.  The dense coarse matrix of small Q1 levels (mode 0) is
+    deterministic."""
+    from paper_1902_08112_amd import PF_F32, PF_F64, pff
+    s, U, phit, act, H, S = setup_case(name, seed=53)
+    E = gpu_solver(s)
+    for X in (S, E):
+        X.set_coarse_mode(coarse)
+        if tiles is not None:
+            # marching tiles or slabs for B~ on every level, the smoother steps fused into them
+            for l in range(s["n_levels"]):
+                for prec in (PF_F64, PF_F32):
+                    pff.pf_set_tuning(X.ctx, l, prec, 1, tiles[0], tiles[1])
+            X.set_smoother_fusion(pff.PF_FUSE_ALWAYS)
+    S.set_graphs(True)
+    E.set_graphs(False)
+    r = np.random.default_rng(59).uniform(-1, 1, H.fine.n_dofs)
+    rd = dev(r)
+    c0 = S.graph_captures()
+    exact_coarse = coarse == 0 and s["degree"] == 1
+    for k in range(4):
+        Uk, phk = W.random_linearization(s, 70 + k)
+        actk = W.random_active(s, 80 + k, 0.05 + 0.04 * k)
+        for X in (S, E):
+            X.set_linearization(dev(Uk), dev(phk), dev(actk))
+        if k == 2:
+            # bounds injected on the finest level (wider interval): device coefficients change
+            b = E.eig_bounds(-1)
+            wide = [b[0], 1.25 * b[1], b[2], 1.25 * b[3]]
+            for X in (S, E):
+                X.set_eig_bounds(-1, wide)
+        if k == 3:
+            H.set_linearization(Uk, phk, actk)
+            inject_bounds(S, H)
+            inject_bounds(E, H)
+        for prec, tol in ((PF_F64, 1e-12 if exact_coarse else 5e-9), (PF_F32, 2e-6)):
+            z_e = host(E.vcycle(rd, prec))
+            print(f"  linearization {k} prec {prec}: two eager launches differ by "
+                  f"{rel_err(host(E.vcycle(rd, prec)), z_e):.1e}", flush=True)
+            for rep in range(2):
+                z = host(S.vcycle(rd, prec))
+                e = rel_err(z, z_e)
+                print(f"  linearization {k} prec {prec} replay {rep}: rel diff to eager {e:.1e}", flush=True)
+                assert e <= tol
+    z_ref = H.vcycle(r)
+    e = rel_err(host(S.vcycle(rd)), z_ref)
+    print(f"  replay after the last linearization vs oracle: {e:.1e}; captures {S.graph_captures() - c0}",
+          flush=True)
+    assert e <= (1e-11 if exact_coarse else 5e-9)
+    # the first V-cycle of each precision captured; every later linearization replayed
+    assert S.graph_captures() - c0 == 2
+    assert E.graph_captures() == 0
+
+
 @pytest.mark.parametrize("name,prec", [("cfg1_2d_q1_32", "f64"), ("cfg1_2d_q1_32", "f32"), ("small3d", "f64"),
                                        ("small3d_q2", "f32"), ("small_lshape", "f32")])
 def test_newton_step_matches_oracle(name, prec):
