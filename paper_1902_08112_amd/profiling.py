@@ -5,6 +5,8 @@
     python -m paper_1902_08112_amd.profiling traffic --fetch <counter_collection.csv>
         --write <counter_collection.csv> --kernel NAME --grid N --copy-bytes B --algorithmic-bytes A
         --workload W --out <traffic.json> --command "<...>" --sources f1 f2 ...
+    python -m paper_1902_08112_amd.profiling counters --csv <counter_collection.csv> --kernel NAME
+        [--kernel NAME ...] [--grid N] --out <summary.md> --command "<...>"
 
 stats: duration statistics per kernel (and, for one kernel at one grid size,
 the per-dispatch mean that the bench's live HIP-event measurement is compared
@@ -16,6 +18,12 @@ copy of copy_bytes that bench.py runs after its timed region (the counters
 cover part of the memory channels; the copy's known size calibrates them).
 The record carries a hash of the kernel's source files: bench.py reports the
 traffic only while the sources are unchanged.
+
+counters: the mean per dispatch of every counter of a --pmc pass for each named
+kernel (at its largest grid, the finest level, or the one asked for), with the
+per-wave ratios of the SQ counters when they are present: instructions per wave,
+and the fractions of the waves' lifetime (SQ_WAVE_CYCLES) spent issuing VALU,
+waiting on any instruction and waiting on LDS.
 """
 from __future__ import annotations
 
@@ -119,14 +127,27 @@ def counter_values(path, counter, kernel, grid):
     return vals
 
 
+def largest_grid(path, kernel):
+    """The largest grid at which a kernel (regex on the short name) was dispatched in a counter CSV."""
+    grids = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if re.search(kernel, short(_col(r, "Kernel_Name"))):
+                grids.append(_grid(r))
+    return max(grids) if grids else None
+
+
 def traffic(a):
-    kern = re.escape(a.kernel)
-    out = {"workload": a.workload, "kernel": a.kernel, "grid": a.grid, "command": a.command,
+    kern = "^" + re.escape(a.kernel) + "$"
+    # without a grid: the kernel's finest level, and the largest copy (one fine-level vector)
+    grid = a.grid if a.grid is not None else largest_grid(a.fetch, kern)
+    copy_grid = a.copy_grid if a.copy_grid is not None else largest_grid(a.fetch, a.copy_kernel)
+    out = {"workload": a.workload, "kernel": a.kernel, "grid": grid, "command": a.command,
            "sources": a.sources, "sources_sha": sources_sha(a.sources)}
     tot = 0.0
     for counter, path in (("FETCH_SIZE", a.fetch), ("WRITE_SIZE", a.write)):
-        k = counter_values(path, counter, "^" + kern + "$", a.grid)
-        c = counter_values(path, counter, a.copy_kernel, a.copy_grid)
+        k = counter_values(path, counter, kern, grid)
+        c = counter_values(path, counter, a.copy_kernel, copy_grid)
         if not k or not c:
             raise SystemExit(f"{counter}: no samples for the kernel ({len(k)}) or the copy ({len(c)})")
         kk, cc = statistics.median(k), statistics.median(c)
@@ -141,6 +162,50 @@ def traffic(a):
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
+
+
+def counter_table(path):
+    """{(kernel, grid): {counter: [value per dispatch]}} of a counter-collection CSV."""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            key = (short(_col(r, "Kernel_Name")), _grid(r))
+            out.setdefault(key, {}).setdefault(_col(r, "Counter_Name"), []).append(float(_col(r, "Counter_Value")))
+    return out
+
+
+# per-wave ratios: (label, numerator, denominator)
+SQ_RATIOS = [("VALU instructions per wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+             ("LDS instructions per wave", "SQ_INSTS_LDS", "SQ_WAVES"),
+             ("wave lifetime per wave (SQ_WAVE_CYCLES units)", "SQ_WAVE_CYCLES", "SQ_WAVES"),
+             ("VALU busy / lifetime", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"),
+             ("waiting on any instruction / lifetime", "SQ_WAIT_INST_ANY", "SQ_WAVE_CYCLES"),
+             ("waiting on LDS / lifetime", "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES"),
+             ("LDS bank-conflict cycles per LDS instruction", "SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS")]
+
+
+def counters(a):
+    tab = counter_table(a.csv)
+    lines = [f"# Counters per dispatch: {os.path.basename(a.out)}", "",
+             "Command (from the repository root on the GPU box):", "", "```", a.command, "```", ""]
+    for kname in a.kernel:
+        grids = [g for (n, g) in tab if n == kname]
+        if not grids:
+            raise SystemExit(f"no dispatches of {kname}")
+        g = a.grid if a.grid is not None else max(grids)
+        cs = tab.get((kname, g))
+        if not cs:
+            raise SystemExit(f"no dispatches of {kname} at grid {g}")
+        mean = {c: statistics.mean(v) for c, v in cs.items()}
+        lines += [f"## `{kname}` at grid {g} ({max(len(v) for v in cs.values())} dispatches)", "",
+                  "| counter | mean per dispatch |", "|---|---:|"]
+        lines += [f"| {c} | {mean[c]:.6g} |" for c in sorted(mean)]
+        rat = [(lab, mean[n] / mean[d]) for lab, n, d in SQ_RATIOS if n in mean and d in mean and mean[d] > 0]
+        if rat:
+            lines += ["", "| ratio | value |", "|---|---:|"] + [f"| {lab} | {v:.4g} |" for lab, v in rat]
+        lines.append("")
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines))
 
 
 def main(argv=None):
@@ -166,8 +231,14 @@ def main(argv=None):
     t.add_argument("--out", required=True)
     t.add_argument("--command", required=True)
     t.add_argument("--sources", nargs="+", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--grid", type=int)
+    c.add_argument("--out", required=True)
+    c.add_argument("--command", required=True)
     a = ap.parse_args(argv)
-    (stats if a.cmd == "stats" else traffic)(a)
+    {"stats": stats, "traffic": traffic, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -74,6 +74,15 @@ def test_traffic_scaled_by_copy(tmp_path):
     assert rec["hbm_bytes_per_launch"] == pytest.approx(409600 + 51200)
     assert rec["traffic_over_algorithmic"] == pytest.approx((409600 + 51200) / 409600)
     assert rec["sources_sha"] == profiling.sources_sha(["paper_1902_08112_amd/csrc/vec.hip"])
+    # without grids: the kernel's largest grid and the largest copy, as chosen above by hand
+    out2 = tmp_path / "t2.json"
+    profiling.main(["traffic", "--fetch", str(tmp_path / "f.csv"), "--write", str(tmp_path / "w.csv"),
+                    "--kernel", "k_x<double>", "--copy-kernel", "copyBuffer", "--copy-bytes", str(1024 * 1024),
+                    "--algorithmic-bytes", "409600", "--workload", "w", "--out", str(out2), "--command", "cmd",
+                    "--sources", "paper_1902_08112_amd/csrc/vec.hip"])
+    rec2 = json.loads(out2.read_text())
+    assert rec2["grid"] == 4096
+    assert rec2["hbm_bytes_per_launch"] == pytest.approx(rec["hbm_bytes_per_launch"])
 
 
 def test_traffic_without_samples_fails(tmp_path):
@@ -85,3 +94,27 @@ def test_traffic_without_samples_fails(tmp_path):
                         "--kernel", "k_y", "--copy-kernel", "copyBuffer", "--copy-bytes", "1",
                         "--algorithmic-bytes", "1", "--workload", "w", "--out", str(tmp_path / "t.json"),
                         "--command", "cmd", "--sources", "paper_1902_08112_amd/csrc/vec.hip"])
+
+
+def test_counters_means_and_sq_ratios(tmp_path):
+    header = ["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"]
+    rows = []
+    for v in (1.0, 3.0):  # two dispatches at the finest grid
+        rows += [["void pff::k_q<double, 0>(CellParams)", 4096, "SQ_WAVES", 10 * v],
+                 ["void pff::k_q<double, 0>(CellParams)", 4096, "SQ_INSTS_VALU", 1000 * v],
+                 ["void pff::k_q<double, 0>(CellParams)", 4096, "SQ_WAVE_CYCLES", 4000 * v],
+                 ["void pff::k_q<double, 0>(CellParams)", 4096, "SQ_ACTIVE_INST_VALU", 1000 * v]]
+    rows += [["void pff::k_q<double, 0>(CellParams)", 64, "SQ_WAVES", 1.0]]   # a coarser level: ignored
+    _write_csv(tmp_path / "c.csv", header, rows)
+    out = tmp_path / "c.md"
+    profiling.main(["counters", "--csv", str(tmp_path / "c.csv"), "--kernel", "k_q<double, 0>",
+                    "--out", str(out), "--command", "cmd"])
+    text = out.read_text()
+    assert "## `k_q<double, 0>` at grid 4096 (2 dispatches)" in text
+    assert "| SQ_WAVES | 20 |" in text
+    assert "| VALU instructions per wave | 100 |" in text
+    assert "| VALU busy / lifetime | 0.25 |" in text
+    assert "LDS instructions per wave" not in text
+    with pytest.raises(SystemExit):
+        profiling.main(["counters", "--csv", str(tmp_path / "c.csv"), "--kernel", "k_missing",
+                        "--out", str(out), "--command", "cmd"])
