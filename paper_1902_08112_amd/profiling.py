@@ -188,14 +188,15 @@ def counters(a):
     tab = counter_table(a.csv)
     lines = [f"# Counters per dispatch: {os.path.basename(a.out)}", "",
              "Command (from the repository root on the GPU box):", "", "```", a.command, "```", ""]
+    found = 0
     for kname in a.kernel:
         grids = [g for (n, g) in tab if n == kname]
-        if not grids:
-            raise SystemExit(f"no dispatches of {kname}")
-        g = a.grid if a.grid is not None else max(grids)
+        g = a.grid if a.grid is not None or not grids else max(grids)
         cs = tab.get((kname, g))
         if not cs:
-            raise SystemExit(f"no dispatches of {kname} at grid {g}")
+            lines += [f"No dispatches of `{kname}`" + ("" if g is None else f" at grid {g}") + ".", ""]
+            continue
+        found += 1
         mean = {c: statistics.mean(v) for c, v in cs.items()}
         lines += [f"## `{kname}` at grid {g} ({max(len(v) for v in cs.values())} dispatches)", "",
                   "| counter | mean per dispatch |", "|---|---:|"]
@@ -204,6 +205,8 @@ def counters(a):
         if rat:
             lines += ["", "| ratio | value |", "|---|---:|"] + [f"| {lab} | {v:.4g} |" for lab, v in rat]
         lines.append("")
+    if not found:
+        raise SystemExit("none of the kernels was dispatched")
     with open(a.out, "w") as f:
         f.write("\n".join(lines))
 

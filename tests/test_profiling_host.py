@@ -115,6 +115,10 @@ def test_counters_means_and_sq_ratios(tmp_path):
     assert "| VALU instructions per wave | 100 |" in text
     assert "| VALU busy / lifetime | 0.25 |" in text
     assert "LDS instructions per wave" not in text
+    # a kernel that did not run is noted; none at all is an error
+    profiling.main(["counters", "--csv", str(tmp_path / "c.csv"), "--kernel", "k_q<double, 0>", "--kernel",
+                    "k_missing", "--out", str(out), "--command", "cmd"])
+    assert "No dispatches of `k_missing`." in out.read_text()
     with pytest.raises(SystemExit):
         profiling.main(["counters", "--csv", str(tmp_path / "c.csv"), "--kernel", "k_missing",
                         "--out", str(out), "--command", "cmd"])
