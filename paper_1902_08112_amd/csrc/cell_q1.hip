@@ -40,11 +40,15 @@ __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, in
   q1_tile3<T, MODE, TX, TY, CHEB>(cp, zc, bx, by, bz, x, U, phit, mask, y, cf);
 }
 
+// one wavefront per 2D row tile; tiles ordered x fastest (ntx strips per y-chunk), launched as a
+// 1D grid: an XCD's range holds neighbouring strips of a chunk row, which share the cache lines at
+// their common edge (a strip's 64-node row segments do not start on a line boundary)
 template <typename T, int MODE>
-__global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, const T* __restrict__ x,
+__global__ __launch_bounds__(64) void k_q1_2d(CellParams cp, int zc, int ntx, const T* __restrict__ x,
                                               const T* __restrict__ U, const T* __restrict__ phit,
                                               const uint8_t* __restrict__ mask, T* __restrict__ y) {
-  q1_tile2<T, MODE>(cp, zc, (int)blockIdx.x, (int)blockIdx.y, x, U, phit, mask, y);
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  q1_tile2<T, MODE>(cp, zc, (int)(t % ntx), (int)(t / ntx), x, U, phit, mask, y);
 }
 
 // One Q1 cell of the block operator B~ with the phase-field coefficients stored per point
@@ -599,11 +603,11 @@ static pf_status launch_q1(const Geom& g, const CellParams& cp, int mode, const 
   } else {
     const int64_t ntx = q1_tiles2(g.nn[0]);
     const int zc = q1_chunk(g, 0, cp.zc);
-    dim3 grid((unsigned)ntx, (unsigned)((g.nn[1] + zc - 1) / zc), 1);
+    const unsigned grid = (unsigned)(ntx * ((g.nn[1] + zc - 1) / zc));
     if (mode == MODE_APPLY)
-      k_q1_2d<T, MODE_APPLY><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+      k_q1_2d<T, MODE_APPLY><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, x, U, phit, mask, y);
     else
-      k_q1_2d<T, MODE_BLOCK><<<grid, 64, 0, s>>>(cp, zc, x, U, phit, mask, y);
+      k_q1_2d<T, MODE_BLOCK><<<grid, 64, 0, s>>>(cp, zc, (int)ntx, x, U, phit, mask, y);
   }
   PFF_CHECK_LAUNCH();
   return PF_OK;

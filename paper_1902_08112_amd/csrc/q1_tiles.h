@@ -162,9 +162,10 @@ __host__ __device__ constexpr int64_t q1_tiles2(int nodes_x) { return (nodes_x +
 
 // One row tile bx and y-chunk by of a 2D Q1 level (the body of k_q1_2d; the batched solver runs
 // it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.  The wavefront
-// marches up the node rows: each lane loads its own node of the next row once (a contiguous
+// marches up the node rows: each lane loads its own node of each row once (a contiguous
 // 64-node segment per field), takes the right-hand corners from lane i + 1 by a shuffle and the
-// lower row from the registers of the previous step.  STORED as for q1_tile3.
+// lower row from the registers of the previous step.  (Loading one row further ahead measured
+// 1.5-3% slower: three waves per SIMD already cover the load latency.)  STORED as for q1_tile3.
 template <typename T, int MODE, bool STORED = true>
 __device__ __forceinline__ void q1_tile2(const CellParams& cp, int zc, int bx, int by, const T* __restrict__ x,
                                          const T* __restrict__ U, const T* __restrict__ phit,
