@@ -557,6 +557,11 @@ def main():
         "apply_dofs_per_s_fp64": n_dofs / t_apply,
         "apply_dofs_per_s_fp32": n_dofs / t_apply32,
         "apply_hbm_frac_fp64": round(rule_bytes / t_apply / 1e9 / HBM_PEAK_GBS, 5),
+        # the largest fraction of HBM peak the FP64 apply could reach with its flops at the FP64
+        # VALU peak (1 where the bytes bind, below 1 where the flops do)
+        "apply_hbm_frac_ceiling_fp64": None if not flops else round(
+            ((rule_bytes + (extra or 0.0)) / HBM_PEAK_GBS / 1e9)
+            / max((rule_bytes + (extra or 0.0)) / HBM_PEAK_GBS / 1e9, flops / FP64_PEAK_TFLOPS / 1e12), 5),
         "newton_s_fp64": t64,
         "newton_s_fp32_vcycle": t32,
         "fp32_vcycle_speedup": t64 / t32,

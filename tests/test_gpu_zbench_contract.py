@@ -45,6 +45,11 @@ def test_bench_line_small3d():
     # small3d is a 3D Q1 mesh: its Jacobian apply is bound by FP64 VALU
     assert roof["kernel"] == d["kernels"]["jacobian"]["kernel"] and roof["bound"] == "alu"
     assert roof["hbm_frac"] == pytest.approx(roof["bytes_per_launch"] / roof["kernel_s_mean"] / 8e12, rel=1e-3, abs=1e-5)
+    # 3D Q1: 2,496 flop against 26.25 B per DoF, so at the FP64 peak the apply moves bytes at
+    # (bytes / 8 TB/s) / (flops / 78.6 TF/s) of the HBM peak; the measured fraction stays below it
+    ceil = d["apply_hbm_frac_ceiling_fp64"]
+    assert 0 < ceil < 1 and d["apply_hbm_frac_fp64"] <= ceil
+    assert ceil == pytest.approx((roof["bytes_per_launch"] / 8e12) / (roof["flop_per_launch"] / 78.6e12), rel=1e-3)
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["unit"] == "DoFs/s" and cpu["cores"] == 1 and cpu["value"] > 0
     assert "8^3" in cpu["sample"]
