@@ -59,8 +59,10 @@ struct Q2Lds {
   T tb[3][3], td[3][3];  // B and D (or their squares for the diagonal)
   T s[3][kQ2Cells + 1][3][3][3];
   // per thread and Gauss point: g(phi~) JxW, the phase-field coefficient, the coupling tensor
-  // (6); written and read by the same thread only (parked here to bound live registers)
-  T q[kQ2Cells + 1][9][3][8];
+  // (6); written and read by the same thread only (parked here to bound live registers).
+  // Lane index fastest: a wavefront's accesses are 64 consecutive values, free of bank
+  // conflicts (a per-thread row of 24 values put every lane on the same two banks).
+  T q[3][8][64];
 };
 
 // Forward contraction of one scalar field.  col[az] = f(tx, ty, az).  Output at the
@@ -344,14 +346,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   } else {
     // park the linearization data of the thread's Gauss points; tau and the coupling term
     // accumulate one direction component at a time (tau is linear in grad du)
-    T (&Q)[3][8] = L.q[cs][tid % 9];
+    auto Q = [&](int qz, int m) -> T& { return L.q[qz][m][tid]; };
 #pragma unroll
     for (int qz = 0; qz < 3; ++qz) {
-      Q[qz][0] = kStored ? gdeg[qz] : gdeg[qz] * jxw[qz];
-      Q[qz][1] = cphi[qz];
+      Q(qz, 0) = kStored ? gdeg[qz] : gdeg[qz] * jxw[qz];
+      Q(qz, 1) = cphi[qz];
       if (kCouple)
 #pragma unroll
-        for (int m = 0; m < 6; ++m) Q[qz][2 + m] = Ksym[qz][m];
+        for (int m = 0; m < 6; ++m) Q(qz, 2 + m) = Ksym[qz][m];
 #pragma unroll
       for (int m = 0; m < 6; ++m) tau[qz][m] = T(0);
     }
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       q2_forward<T, true>(L, k, cs, tx, ty, col, ih, v, gdc);
 #pragma unroll
       for (int qz = 0; qz < 3; ++qz) {
-        const T w = Q[qz][0];
+        const T w = Q(qz, 0);
         const T tl = w * lam * gdc[c][qz];
         tau[qz][0] += tl;
         tau[qz][1] += tl;
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         if (kCouple) {
           T f = T(0);
 #pragma unroll
-          for (int j = 0; j < 3; ++j) f += Q[qz][2 + kSym[c][j]] * gdc[j][qz];
+          for (int j = 0; j < 3; ++j) f += Q(qz, 2 + kSym[c][j]) * gdc[j][qz];
           fcpl[qz] += f;
         }
       }
@@ -418,10 +420,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
     T dpv[3], gdp[3][3];
     q2_forward<T, true>(L, k, cs, tx, ty, col, ih, dpv, gdp);
-    const T (&Q)[3][8] = L.q[cs][tid % 9];
 #pragma unroll
     for (int qz = 0; qz < 3; ++qz) {
-      cv[qz] = (Q[qz][1] * dpv[qz] + fcpl[qz]) * jxw[qz];
+      cv[qz] = (L.q[qz][1][tid] * dpv[qz] + fcpl[qz]) * jxw[qz];
 #pragma unroll
       for (int j = 0; j < 3; ++j) cg[j][qz] = gcx * gdp[j][qz] * jxw[qz] * ih[j];
     }
