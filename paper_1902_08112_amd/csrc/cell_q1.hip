@@ -25,8 +25,9 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
-// one wavefront per tile; tiles ordered z-chunk fastest, then x, then y (ntx x nty tiles of
-// TX x TY cells, nzc chunks), launched as a 1D grid of ntx * nty * nzc workgroups
+// one wavefront per tile; tiles ordered x fastest, then y, then z-chunk (ntx x nty tiles of
+// TX x TY cells, nzc chunks), launched as a 1D grid of ntx * nty * nzc workgroups: an XCD's range
+// holds neighbouring tiles of a chunk layer, which share their edge lines in one L2
 // CHEB (block operator only): instead of y, apply the Chebyshev step cf at every owned node.
 template <typename T, int MODE, int TX, int TY, bool CHEB = false>
 __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, int nzc, const T* __restrict__ x,
@@ -34,9 +35,10 @@ __global__ __launch_bounds__(64) void k_q1_3d(CellParams cp, int zc, int ntx, in
                                               const uint8_t* __restrict__ mask, T* __restrict__ y,
                                               ChebFuse<T> cf = ChebFuse<T>{}) {
   const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
-  const int bz = (int)(t % nzc);
-  const int bx = (int)((t / nzc) % ntx);
-  const int by = (int)(t / ((int64_t)nzc * ntx));
+  const int64_t tiles = (int64_t)gridDim.x / nzc;
+  const int bx = (int)(t % ntx);
+  const int by = (int)((t / ntx) % (tiles / ntx));
+  const int bz = (int)(t / tiles);
   q1_tile3<T, MODE, TX, TY, CHEB>(cp, zc, bx, by, bz, x, U, phit, mask, y, cf);
 }
 
@@ -115,7 +117,8 @@ __global__ __launch_bounds__(128) void k_q1_3d_atomic(CellParams cp, const T* __
                                                       const T* __restrict__ U, const T* __restrict__ phit,
                                                       const uint8_t* __restrict__ mask, T* __restrict__ y) {
   constexpr bool COUPLE = (MODE == MODE_APPLY);
-  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one contiguous range of cells per XCD (neighbouring cells share nodes)
+  const int64_t cid = xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (cid >= cp.n_cells) return;
   const int cx = (int)(cid % cp.N[0]);
   const int cy = (int)((cid / cp.N[0]) % cp.N[1]);

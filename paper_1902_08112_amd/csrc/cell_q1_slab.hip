@@ -267,10 +267,13 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
 #pragma unroll
     for (int k = 0; k < 4; ++k) cc[k] = (T)cf.dc[k];
   }
+  // tiles x-fastest, then y, then z-chunk: an XCD's range holds neighbouring slabs of a chunk
+  // layer, which share the cache lines of their common edge rows and columns in one L2
   const int64_t t = xcd_tile_s(blockIdx.x, gridDim.x);
-  const int bz = (int)(t % nzc);
-  const int bx = (int)((t / nzc) % ntx);
-  const int by = (int)(t / ((int64_t)nzc * ntx));
+  const int64_t tiles = (int64_t)gridDim.x / nzc;
+  const int bx = (int)(t % ntx);
+  const int by = (int)((t / ntx) % (tiles / ntx));
+  const int bz = (int)(t / tiles);
   const int tid = threadIdx.x;
   const int i = tid % kSX, j = tid / kSX;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);

@@ -192,7 +192,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   const Q2Tab<T> k;
   q2_fill_tables(L.tb, L.td, tid, false);
   __syncthreads();
-  const int64_t cid = (int64_t)blockIdx.x * kQ2Cells + tid / 9;
+  // workgroups are dealt to the 8 XCDs round-robin: give each XCD one contiguous range of cell
+  // groups, so that neighbouring cells read their shared nodes through one L2
+  const int64_t nb = gridDim.x, qq = nb / 8, rr = nb % 8, xcd = blockIdx.x % 8;
+  const int64_t grp = xcd * qq + (xcd < rr ? xcd : rr) + blockIdx.x / 8;
+  const int64_t cid = grp * kQ2Cells + tid / 9;
   bool active = tid < 9 * kQ2Cells && cid < cp.n_cells;
   int cx = 0, cy = 0, cz = 0;
   if (active) {
