@@ -17,7 +17,7 @@
 // overlap by one cell in x and y (and chunks by one cell layer in z); a lane whose node has a
 // neighbouring cell outside the tile owns nothing.  Every node is written once with a plain
 // store, identity rows included; the result is deterministic.  One barrier per cell layer.
-#include "q1_cell.h"
+#include "q1_tiles.h"
 
 namespace pff {
 
@@ -248,12 +248,14 @@ __device__ __forceinline__ void phi_rows_layers(const Consts<T>& k, const T (*pl
 
 }  // namespace
 
+// Occupancy: the FP64 Jacobian and the FP64 fused step keep 256 registers at 2 waves per SIMD
+// (at 3 they spill heavily); the FP32 kernels and the plain FP64 B~ fit 168 registers with at
+// most 40 B of spill and run at 3 waves (FP32 G~ 10% and FP64 B~ 3% faster on 256^3).
 template <typename T, int MODE, bool CHEB>
-__global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_q1_3d_slab(CellParams cp, int zc, int ntx, int nzc,
-                                                          const T* __restrict__ x, const T* __restrict__ U,
-                                                          const T* __restrict__ phit,
-                                                          const uint8_t* __restrict__ mask, T* __restrict__ y,
-                                                          ChebFuse<T> cf) {
+__global__ __launch_bounds__(kSThreads)
+__attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHEB)) ? 2 : 3))) void k_q1_3d_slab(
+    CellParams cp, int zc, int ntx, int nzc, const T* __restrict__ x, const T* __restrict__ U,
+    const T* __restrict__ phit, const uint8_t* __restrict__ mask, T* __restrict__ y, ChebFuse<T> cf) {
   static_assert(!CHEB || MODE == MODE_BLOCK, "the fused Chebyshev step follows the block operator");
   using F = SlabFields<MODE>;
   constexpr bool COUPLE = (MODE == MODE_APPLY);
@@ -284,6 +286,10 @@ __global__ __launch_bounds__(kSThreads) __attribute__((amdgpu_waves_per_eu(2))) 
   const int z_hi = min(z_lo + zc, cp.nn[2]);
   const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
   const bool own_xy = i >= 1 && j >= 1 && cx <= cp.nn[0] - 1 && cy <= cp.nn[1] - 1;
+  if (q1_hole_tile(cp, gx0, gy0)) {  // uniform over the workgroup: no barrier has run yet
+    q1_hole_rows3<T, CHEB>(cp, own_xy, cx, cy, z_lo, z_hi, x, mask, y, cf, cc);
+    return;
+  }
   const bool cell_xy = cx >= 0 && cx < cp.N[0] && cy >= 0 && cy < cp.N[1] &&
                        !cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1]);
   const int ln = i + j * kSNX;  // the lane's node (lower corner of its cell) in the tile plane

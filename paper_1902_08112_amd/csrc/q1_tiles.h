@@ -33,6 +33,44 @@ __device__ __forceinline__ void combine3(const T out[8], T carry, T& val, T& nca
 // One TX x TY marching tile (bx, by) and z-chunk bz of a 3D Q1 level (the body of k_q1_3d; the
 // batched solver runs it for one instance's tile per work item).  One wavefront, lane = threadIdx.x.
 // STORED (block operator): read c_phi JxW per Gauss point from cp.qcb; otherwise form it from U.
+// A 3D tile whose cells all lie in the L-shape's hole (2 cx >= N0 and 2 cy >= N1 from its first
+// cell on) has no cell work: its owned nodes are hole nodes, and the cell loop over no cells leaves
+// each row at its identity (constrained) or 0 -- written here without streaming anything else.
+// cx0, cy0: the tile's first cell.
+__device__ __forceinline__ bool q1_hole_tile(const CellParams& cp, int cx0, int cy0) {
+  return cp.lshape && cx0 >= 0 && cy0 >= 0 && 2 * cx0 >= cp.N[0] && 2 * cy0 >= cp.N[1];
+}
+template <typename T, bool CHEB>
+__device__ __forceinline__ void q1_hole_rows3(const CellParams& cp, bool own_xy, int cx, int cy, int z_lo, int z_hi,
+                                              const T* __restrict__ x, const uint8_t* __restrict__ mask,
+                                              T* __restrict__ y, const ChebFuse<T>& cf, const T (&cc)[4]) {
+  if (!own_xy) return;
+  const int64_t nn = cp.n_nodes, sy = cp.ns[1], sz = cp.ns[2];
+  for (int kz = z_lo; kz < z_hi; ++kz) {
+    const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+    const uint8_t m = mask[go];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t o = c * nn + go;
+      const bool con = m & mask_bit(c, 3);
+      if constexpr (CHEB) {
+        // the fused Chebyshev step with (B~ d)(node) = Pi_C d
+        const T c1 = c == 3 ? cc[2] : cc[0], c2 = c == 3 ? cc[3] : cc[1];
+        const T d = x[o];
+        const T r = cf.res[o] - (con ? d : T(0));
+        cf.res[o] = r;
+        const T dn = c1 * d + c2 * r / cf.diag[o];
+        const T xn = cf.x[o] + dn;
+        cf.x[o] = xn;
+        if (cf.d_out) cf.d_out[o] = dn;
+        if (cf.t_next) cf.t_next[o] = con ? (cf.next_of_x ? xn : dn) : T(0);
+      } else {
+        y[o] = con ? x[o] : T(0);
+      }
+    }
+  }
+}
+
 template <typename T, int MODE, int TX, int TY, bool CHEB, bool STORED = true>
 __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, int by, int bz, const T* __restrict__ x,
                                          const T* __restrict__ U, const T* __restrict__ phit,
@@ -57,6 +95,10 @@ __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, i
   if constexpr (CHEB) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) cc[k] = (T)cf.dc[k];
+  }
+  if (q1_hole_tile(cp, bx * (TX - 1) - 1, by * (TY - 1) - 1)) {
+    q1_hole_rows3<T, CHEB>(cp, own_xy, cx, cy, z_lo, z_hi, x, mask, y, cf, cc);
+    return;
   }
   T carry[4] = {T(0), T(0), T(0), T(0)};
   for (int kz = z_lo - 1; kz < z_hi; ++kz) {
