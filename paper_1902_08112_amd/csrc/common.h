@@ -285,6 +285,9 @@ pf_status constrain_rhs(const Geom& g, const double* R, const double* t, const d
                         double* Rt, hipStream_t s);
 
 constexpr int kRedBlock = 256;
-constexpr int kRedMaxBlocks = 1024;
+constexpr int kRedMaxBlocks = 4096;  // enough wavefronts in flight to stream a 50M-value vector
+// multi_dot: rows per launch, and workgroups per launch (its partials need kMultiDotBlocks per row)
+constexpr int kMultiDotRows = 8;
+constexpr int kMultiDotBlocks = 2048;
 
 }  // namespace pff

@@ -106,17 +106,18 @@ pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, co
 // y = constrained ? 0 : x  (with type conversion)
 template <typename Tin, typename Tout>
 __global__ void k_mask_free(Tout* y, const Tin* x, const uint8_t* mask, int64_t nn, int d) {
-  const int64_t n = (int64_t)(d + 1) * nn;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i / nn);
-    const int64_t node = i - (int64_t)c * nn;
-    y[i] = (mask[node] & mask_bit(c, d)) ? Tout(0) : (Tout)x[i];
+  // node-major: one mask byte per node, the components without a 64-bit division per value
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nn; j += (int64_t)gridDim.x * blockDim.x) {
+    const uint8_t m = mask[j];
+    for (int c = 0; c <= d; ++c) {
+      const int64_t i = (int64_t)c * nn + j;
+      y[i] = (m & mask_bit(c, d)) ? Tout(0) : (Tout)x[i];
+    }
   }
 }
 template <typename Tin, typename Tout>
 pf_status mask_free(Tout* y, const Tin* x, const uint8_t* mask, int64_t nn, int d, hipStream_t s) {
-  int64_t n = (int64_t)(d + 1) * nn;
-  int64_t nb = std::min<int64_t>(65536, std::max<int64_t>(1, (n + 255) / 256));
+  int64_t nb = std::min<int64_t>(65536, std::max<int64_t>(1, (nn + 255) / 256));
   k_mask_free<Tin, Tout><<<nb, 256, 0, s>>>(y, x, mask, nn, d);
   PFF_CHECK_LAUNCH();
   return PF_OK;
@@ -459,7 +460,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   double* V = cv.take<double>((size_t)(mr + 1) * nd);
   double* Z = cv.take<double>((size_t)mr * nd);
   double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
-  double* part_md = cv.take<double>((size_t)256 * (mr + 2));
+  double* part_md = cv.take<double>((size_t)kMultiDotBlocks * (mr + 2));
   double* dscal = cv.take<double>(1024);
   EigDev* eigdev = cv.take<EigDev>(L);
   double* part_lev = cv.take<double>((size_t)L * kPartStride);

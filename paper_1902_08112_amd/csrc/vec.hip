@@ -247,15 +247,22 @@ pf_status nrm2_dev(const double* x, int64_t n, double* d_part, double* d_out, hi
   return dot_segments(x, x, b, 1, d_part, d_out, s);
 }
 
-// multi-dot: grid (nb, k); partials[i * nb + block]
-__global__ void k_multi_dot(const double* V, int64_t ld, const double* w, int64_t n, double* partials) {
-  const int i = blockIdx.y;
-  const double* v = V + (int64_t)i * ld;
-  double acc = 0.0;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-    acc += v[t] * w[t];
-  const double b = block_sum(acc);
-  if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = b;
+// multi-dot: h[i] = V_i . w for i < k.  A thread reads w once and accumulates up to kMultiDotRows
+// dots; partials[i * nb + block] (rows beyond one launch's kMultiDotRows take further launches).
+__global__ void k_multi_dot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* partials) {
+  double acc[kMultiDotRows];
+#pragma unroll
+  for (int i = 0; i < kMultiDotRows; ++i) acc[i] = 0.0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    const double wt = w[t];
+#pragma unroll
+    for (int i = 0; i < kMultiDotRows; ++i)
+      if (i < k) acc[i] += V[(int64_t)i * ld + t] * wt;
+  }
+  for (int i = 0; i < k; ++i) {
+    const double b = block_sum(acc[i]);
+    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = b;
+  }
 }
 
 __global__ void k_finalize_rows(const double* partials, int nparts, double* out) {
@@ -266,12 +273,16 @@ __global__ void k_finalize_rows(const double* partials, int nparts, double* out)
   if (threadIdx.x == 0) out[k] = b;
 }
 
+// d_part holds kMultiDotBlocks * k doubles
 pf_status multi_dot(const double* V, int64_t ld, int k, const double* w, int64_t n, double* d_part, double* d_h,
                     hipStream_t s) {
-  int nb = (int)nblocks(n, kRedBlock, 256);
-  dim3 grid(nb, k);
-  k_multi_dot<<<grid, kRedBlock, 0, s>>>(V, ld, w, n, d_part);
-  PFF_CHECK_LAUNCH();
+  // at least 8 values per thread (small vectors: fewer partials to finish), at most kMultiDotBlocks
+  const int nb = (int)nblocks(n, kRedBlock * 8, kMultiDotBlocks);
+  for (int r0 = 0; r0 < k; r0 += kMultiDotRows) {
+    const int kr = std::min(kMultiDotRows, k - r0);
+    k_multi_dot<<<nb, kRedBlock, 0, s>>>(V + (int64_t)r0 * ld, ld, kr, w, n, d_part + (int64_t)r0 * nb);
+    PFF_CHECK_LAUNCH();
+  }
   k_finalize_rows<<<k, kRedBlock, 0, s>>>(d_part, nb, d_h);
   PFF_CHECK_LAUNCH();
   return PF_OK;
@@ -397,30 +408,32 @@ pf_status vec_axpy_blocks(double* y, const double* x, const double alpha[2], int
 template <typename T>
 __global__ void k_eig_precond(T* r, const T* q, const EigDev* st, T* z, T* p, const T* diag,
                               const uint8_t* mask, int64_t nn, int d, double* partials) {
-  const int64_t nu = (int64_t)d * nn, n = nu + nn;
+  // node-major: a thread takes a node and the components of one block, so the component of an
+  // index needs no 64-bit division
   for (int k = 0; k < 2; ++k) {
-    const int64_t lo = k == 0 ? 0 : nu, hi = k == 0 ? nu : n;
+    const int c0 = k == 0 ? 0 : d, c1 = k == 0 ? d : d + 1;
     const T na = q ? T(-st->alpha[k]) : T(0);
     double acc = 0.0;
-    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
-         i += (int64_t)gridDim.x * blockDim.x) {
-      T ri = r[i];
-      if (q) {
-        ri += na * q[i];
-        r[i] = ri;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nn; j += (int64_t)gridDim.x * blockDim.x) {
+      const uint8_t m = mask[j];
+      for (int c = c0; c < c1; ++c) {
+        const int64_t i = (int64_t)c * nn + j;
+        T ri = r[i];
+        if (q) {
+          ri += na * q[i];
+          r[i] = ri;
+        }
+        const T zi = (m & mask_bit(c, d)) ? T(0) : ri / diag[i];
+        z[i] = zi;
+        if (p) p[i] = zi;
+        acc += (double)ri * (double)zi;
       }
-      const int c = (int)(i / nn);
-      const T zi = (mask[i - (int64_t)c * nn] & mask_bit(c, d)) ? T(0) : ri / diag[i];
-      z[i] = zi;
-      if (p) p[i] = zi;
-      acc += (double)ri * (double)zi;
     }
     const double b = block_sum(acc);
     if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = b;
   }
 }
 
-// phase 0: start; 1: alpha from (p, Ap); 2: beta from the new (r, z)
 __global__ void k_eig_update(const double* partials, int nparts, EigDev* st, int phase) {
   double tot[2];
   for (int k = 0; k < 2; ++k) {
@@ -468,8 +481,7 @@ __global__ void k_eig_xpby(T* p, const T* z, const EigDev* st, int64_t nu, int64
 template <typename T>
 pf_status eig_cg_begin(const T* r, T* z, T* p, const T* diag, const uint8_t* mask, int64_t nn,
                        int d, double* d_part, EigDev* st, hipStream_t s) {
-  const int64_t n = (int64_t)(d + 1) * nn;
-  const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
+  const int nb = (int)nblocks(nn, kRedBlock, kRedMaxBlocks);
   k_eig_precond<T><<<nb, kRedBlock, 0, s>>>(const_cast<T*>(r), nullptr, st, z, p, diag, mask, nn, d, d_part);
   PFF_CHECK_LAUNCH();
   k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 0);
@@ -493,7 +505,7 @@ template <typename T>
 pf_status eig_cg_beta(T* r, const T* Ap, T* z, T* p, const T* diag, const uint8_t* mask,
                       int64_t nn, int d, double* d_part, EigDev* st, hipStream_t s) {
   const int64_t n = (int64_t)(d + 1) * nn;
-  const int nb = (int)nblocks(n, kRedBlock, kRedMaxBlocks);
+  const int nb = (int)nblocks(nn, kRedBlock, kRedMaxBlocks);
   k_eig_precond<T><<<nb, kRedBlock, 0, s>>>(r, Ap, st, z, nullptr, diag, mask, nn, d, d_part);
   PFF_CHECK_LAUNCH();
   k_eig_update<<<1, kRedBlock, 0, s>>>(d_part, nb, st, 2);
