@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpff.so")
-SOURCES = ["cell_generic.hip", "cell_q1.hip", "cell_q1_slab.hip", "vec.hip", "grid.hip", "solver.hip", "batch.hip", "coarse.hip", "cell_q2.hip", "quantities.hip", "cell_split.hip"]
+SOURCES = ["cell_generic.hip", "cell_q1.hip", "cell_q1_slab.hip", "cell_q1_aux.hip", "vec.hip", "grid.hip", "solver.hip", "batch.hip", "coarse.hip", "cell_q2.hip", "quantities.hip", "cell_split.hip"]
 ARCH = "gfx950"
 
 

@@ -1,6 +1,7 @@
 // Q1 cell loops (the fast path of the Jacobian and the smoother operator, Sec. 4.1) for 2D and
 // 3D, FP64 and FP32: the marching tiles (bodies in q1_tiles.h), one thread per cell with atomic
-// scatter, two work items per cell, LDS bricks, and the residual / diagonal / unmasked apply.
+// scatter, two work items per cell and LDS bricks (the residual and the diagonal are in
+// cell_q1_aux.hip).
 //
 // The cell work is split into a displacement part (test functions w:
 // g(phi~) sigma(du) : e(w)) and a phase-field part (test functions psi), each
@@ -344,94 +345,6 @@ __global__ __launch_bounds__(128) void k_q1_split(CellParams cp, const T* __rest
     q1_cell_atomic<D, T, COUPLE>(cp, g0, x, U, phit, mask, y, part);
 }
 
-// ----------------------------------------------------------------------------------- other modes
-// The residual -A(U), the diagonal of G and the unmasked apply G x on Q1 cells (FP64): one thread
-// per cell, every row, atomic scatter into a zeroed y.
-template <int D, int MODE>
-__global__ __launch_bounds__(128) void k_q1_aux(CellParams cp, const double* __restrict__ x,
-                                                const double* __restrict__ U, const double* __restrict__ phit,
-                                                double* __restrict__ y) {
-  constexpr int NL = D == 3 ? 8 : 4;
-  const int64_t cid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cid >= cp.n_cells) return;
-  const int cx = (int)(cid % cp.N[0]);
-  const int cy = (int)((cid / cp.N[0]) % cp.N[1]);
-  const int cz = D == 3 ? (int)(cid / ((int64_t)cp.N[0] * cp.N[1])) : 0;
-  if (cell_in_hole(cp.lshape, cx, cy, cp.N[0], cp.N[1])) return;
-  const int64_t nn = cp.n_nodes;
-  const int64_t g0 = (int64_t)cx + (int64_t)cy * cp.ns[1] + (int64_t)cz * cp.ns[2];
-  int64_t gi[NL];
-#pragma unroll
-  for (int a = 0; a < NL; ++a) gi[a] = g0 + (a & 1) + ((a >> 1) & 1) * cp.ns[1] + (D == 3 ? (a >> 2) * cp.ns[2] : 0);
-  const Consts<double> kc(cp, NL);
-  double uu[D][NL], ph[NL], pt[NL];
-#pragma unroll
-  for (int a = 0; a < NL; ++a) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) uu[c][a] = U[c * nn + gi[a]];
-    ph[a] = U[D * nn + gi[a]];
-    pt[a] = phit[gi[a]];
-  }
-  double ou[D][NL], op[NL];
-  if constexpr (MODE == MODE_RESID) {
-    if constexpr (D == 3)
-      cell3_resid<double>(kc, uu, ph, pt, ou, op);
-    else
-      cell2_resid<double>(kc, uu, ph, pt, ou, op);
-  } else if constexpr (MODE == MODE_DIAG) {
-    double gw[NL], cph[NL];
-    if constexpr (D == 3)
-      cell3_diag_coef<double>(kc, uu, pt, gw, cph);
-    else
-      cell2_diag_coef<double>(kc, uu, pt, gw, cph);
-    cell_diag<D, double>(kc, gw, cph, ou, op);
-  } else {
-    double du[D][NL], dp[NL];
-#pragma unroll
-    for (int a = 0; a < NL; ++a) {
-#pragma unroll
-      for (int c = 0; c < D; ++c) du[c][a] = x[c * nn + gi[a]];
-      dp[a] = x[D * nn + gi[a]];
-    }
-    if constexpr (D == 3) {
-      cell3_u<double>(kc, du, pt, ou);
-      cell3_phi<double, true>(kc, du, dp, uu, ph, op);
-    } else {
-      cell2_u<double>(kc, du, pt, ou);
-      cell2_phi<double, true>(kc, du, dp, uu, ph, op);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < NL; ++a) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) atomicAdd(&y[c * nn + gi[a]], ou[c][a]);
-    atomicAdd(&y[D * nn + gi[a]], op[a]);
-  }
-}
-
-static pf_status launch_q1_aux(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
-                               const double* phit, double* y, hipStream_t s) {
-  const int64_t nb = (g.n_cells + 127) / 128;
-  if (nb == 0) return PF_OK;
-  if (g.d == 3) {
-    if (mode == MODE_RESID)
-      k_q1_aux<3, MODE_RESID><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-    else if (mode == MODE_DIAG)
-      k_q1_aux<3, MODE_DIAG><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-    else
-      k_q1_aux<3, MODE_RAW><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-  } else {
-    if (mode == MODE_RESID)
-      k_q1_aux<2, MODE_RESID><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-    else if (mode == MODE_DIAG)
-      k_q1_aux<2, MODE_DIAG><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-    else
-      k_q1_aux<2, MODE_RAW><<<nb, 128, 0, s>>>(cp, x, U, phit, y);
-  }
-  PFF_CHECK_LAUNCH();
-  return PF_OK;
-}
-
 // ----------------------------------------------------------------------------------- B~ coefficients
 // c[q * n_cells + cid] = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) JxW at Gauss point q of cell
 // cid, from the level's linearization point U (FP64), stored in FP64 and FP32; 0 in hole cells.
@@ -653,9 +566,9 @@ template pf_status launch_q1_block_cheb<float>(const Geom&, const CellParams&, c
 
 pf_status launch_cell_q1_d(const Geom& g, const CellParams& cp, int mode, const double* x, const double* U,
                            const double* phit, const uint8_t* mask, double* y, hipStream_t s, bool* handled) {
-  if (g.p == 1 && (g.d == 2 || g.d == 3) && (mode == MODE_RAW || mode == MODE_RESID || mode == MODE_DIAG)) {
+  if (q1_aux_handles(g, mode)) {
     *handled = true;
-    return launch_q1_aux(g, cp, mode, x, U, phit, y, s);
+    return launch_q1_aux(g, cp, mode, U, phit, y, s);
   }
   *handled = q1_variant(g, mode, cp.variant) >= 0;
   if (!*handled) return PF_OK;

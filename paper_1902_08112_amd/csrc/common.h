@@ -154,6 +154,12 @@ int q1_variant(const Geom& g, int mode, int requested);
 bool q1_tiled_handles(const Geom& g, int mode, int requested);
 // marching chunk the tiled kernels use for this level and request
 int q1_chunk(const Geom& g, int variant, int requested_zc);
+// FP64 residual -A(U) (MODE_RESID) and diag(G) (MODE_DIAG) on 2D / 3D Q1 levels without the
+// energy split (cell_q1_aux.hip): marching tiles that write every entry of y (no constraint
+// applied, no pre-set y)
+bool q1_aux_handles(const Geom& g, int mode);
+pf_status launch_q1_aux(const Geom& g, const CellParams& cp, int mode, const double* U, const double* phit,
+                        double* y, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // vector kernels (vec.hip)

@@ -90,7 +90,7 @@ static bool tiled_writes_all(const Geom& g, const CellParams& cp, int mode) {
 template <typename T>
 pf_status apply_op(const Geom& g, const CellParams& cp, int mode, const T* x, const T* U, const T* phit,
                    const uint8_t* mask, T* y, hipStream_t s, bool y_preset = false) {
-  if (tiled_writes_all(g, cp, mode)) {
+  if (tiled_writes_all(g, cp, mode) || (sizeof(T) == 8 && !cp.split && q1_aux_handles(g, mode))) {
     // the tiled kernels write every entry, identity rows included
   } else if (starts_from_constrained(mode)) {
     // y = Pi_C x, unless the producer of x already wrote it
@@ -200,6 +200,7 @@ struct pf_ctx {
   std::vector<LevelBuf> lev;
   double *M = nullptr, *R = nullptr, *dl = nullptr, *Rt = nullptr, *dU = nullptr, *t = nullptr;
   uint8_t *extra = nullptr, *active = nullptr, *prev_active = nullptr;
+  uint8_t* free_mask = nullptr;  // finest level, all zero: no DoF constrained
   double *V = nullptr, *Z = nullptr;
   double *part = nullptr, *part_md = nullptr, *dscal = nullptr;
   EigDev* eigdev = nullptr;  // one record per level
@@ -457,6 +458,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
   uint8_t* extra = cv.take<uint8_t>(nn);
   uint8_t* active = cv.take<uint8_t>(nn);
   uint8_t* prev_active = cv.take<uint8_t>(nn);
+  uint8_t* free_mask = cv.take<uint8_t>(nn);
   double* V = cv.take<double>((size_t)(mr + 1) * nd);
   double* Z = cv.take<double>((size_t)mr * nd);
   double* part = cv.take<double>(2 * kRedMaxBlocks + 256);
@@ -483,6 +485,7 @@ size_t carve(pf_ctx* c, const pf_mesh& m, const pf_options& o, char* base) {
     c->extra = extra;
     c->active = active;
     c->prev_active = prev_active;
+    c->free_mask = free_mask;
     c->V = V;
     c->Z = Z;
     c->part = part;
@@ -1237,6 +1240,10 @@ pf_status pf_setup(const pf_mesh* mesh, double E, double nu, double G_c, double 
     }
   }
   pf_status r = lumped_mass(c->lev[L - 1].g, c->M, s);
+  if (r == PF_OK && hipMemsetAsync(c->free_mask, 0, (size_t)c->lev[L - 1].g.n_nodes, s) != hipSuccess) {
+    set_error("clearing the all-free mask failed");
+    r = PF_ERR_DEVICE;
+  }
   if (r != PF_OK) {
     delete c;
     return r;
@@ -1548,7 +1555,13 @@ pf_status newton_prepare(pf_ctx* ctx, const double* d_U, const double* d_U_old, 
   PFF_TRY(combine_mask(f.base, ctx->has_extra ? ctx->extra : nullptr, ctx->active, f.mask, g.n_nodes, s));
   const double* tlift = nullptr;
   if (*n_active > 0) {
-    PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RAW, ctx->dl, d_U, d_phi_tilde, f.mask, ctx->t, s));
+    // t = G d_lift with no constraint applied: on Q1 cells without the energy split the Jacobian's
+    // own (tuned) kernel with the all-free mask, else the unmasked mode of the cell loop
+    const CellParams cpa = level_params(ctx, L, PF_F64, MODE_APPLY);
+    if (g.p == 1 && !cpa.split)
+      PFF_TRY(apply_op<double>(g, cpa, MODE_APPLY, ctx->dl, d_U, d_phi_tilde, ctx->free_mask, ctx->t, s));
+    else
+      PFF_TRY(apply_op<double>(g, cparams(ctx, L), MODE_RAW, ctx->dl, d_U, d_phi_tilde, f.mask, ctx->t, s));
     tlift = ctx->t;
   }
   PFF_TRY(constrain_rhs(g, ctx->R, tlift, ctx->dl, f.mask, ctx->Rt, s));

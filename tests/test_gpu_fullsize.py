@@ -80,6 +80,13 @@ def check_apply(name):
     assert np.isfinite(y).all()
     # full-vector property: identity on every constrained DoF
     assert np.array_equal(y[cons], x[cons])
+    # the Newton residual -A(U) on the same sampled rows (every row, constrained ones included)
+    R = host(S.residual(dev(U), dev(phit)))
+    refR = -model.residual_rows(lev, mat, U, phit, rows)
+    errR = np.abs(R[rows] - refR).max() / np.abs(refR).max()
+    print(f"  residual: max rel err {errR:.2e} on the sampled rows", flush=True)
+    assert errR <= 1e-12
+    assert np.isfinite(R).all()
 
 
 def check_newton(name):
