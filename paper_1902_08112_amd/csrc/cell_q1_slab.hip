@@ -396,6 +396,20 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
     }
     // keep the compiler from carrying the corner values of the first part into the second
     __asm__ __volatile__("" ::: "memory");
+    // the fused step's operands at the lane's own node of plane kz (residual, diagonal, iterate),
+    // requested before the phase-field rows so that their math and the barrier cover the latency
+    T fr[4] = {T(0), T(0), T(0), T(0)}, fd[4] = {T(1), T(1), T(1), T(1)}, fx[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (CHEB) {
+      if (own_xy && kz >= z_lo) {
+        const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          fr[c] = cf.res[c * nn + go];
+          fd[c] = cf.diag[c * nn + go];
+          fx[c] = cf.x[c * nn + go];
+        }
+      }
+    }
     // phase-field rows
     {
       T outp[8];
@@ -472,10 +486,10 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
         if constexpr (CHEB) {
           const T c1 = c == 3 ? cc[2] : cc[0], c2 = c == 3 ? cc[3] : cc[1];
           const T d = xo[c];
-          const T r = cf.res[o] - (con ? d : val);
+          const T r = fr[c] - (con ? d : val);
           cf.res[o] = r;
-          const T dn = c1 * d + c2 * r / cf.diag[o];
-          const T xn = cf.x[o] + dn;
+          const T dn = c1 * d + c2 * r / fd[c];
+          const T xn = fx[c] + dn;
           cf.x[o] = xn;
           if (cf.d_out) cf.d_out[o] = dn;
           if (cf.t_next) cf.t_next[o] = con ? (cf.next_of_x ? xn : dn) : T(0);
