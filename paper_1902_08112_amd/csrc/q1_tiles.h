@@ -132,6 +132,20 @@ __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, i
     T val[4], nc[4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) combine3<T, TX>(outu[c], carry[c], val[c], nc[c]);
+    // the fused step's operands at the lane's own node of plane kz (residual, diagonal, iterate),
+    // requested before the phase-field rows so that their math covers the latency
+    T fr[4] = {T(0), T(0), T(0), T(0)}, fd[4] = {T(1), T(1), T(1), T(1)}, fx[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (CHEB) {
+      if (own_xy && kz >= z_lo) {
+        const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          fr[c] = cf.res[c * nn + go];
+          fd[c] = cf.diag[c * nn + go];
+          fx[c] = cf.x[c * nn + go];
+        }
+      }
+    }
     T outp[8];
     if (cell) {
       if constexpr (MODE == MODE_BLOCK && STORED) {
@@ -171,10 +185,10 @@ __device__ __forceinline__ void q1_tile3(const CellParams& cp, int zc, int bx, i
         if constexpr (CHEB) {
           const T c1 = c == 3 ? cc[2] : cc[0], c2 = c == 3 ? cc[3] : cc[1];
           const T d = x[o];
-          const T r = cf.res[o] - (con ? d : val[c]);
+          const T r = fr[c] - (con ? d : val[c]);
           cf.res[o] = r;
-          const T dn = c1 * d + c2 * r / cf.diag[o];
-          const T xn = cf.x[o] + dn;
+          const T dn = c1 * d + c2 * r / fd[c];
+          const T xn = fx[c] + dn;
           cf.x[o] = xn;
           if (cf.d_out) cf.d_out[o] = dn;
           if (cf.t_next) cf.t_next[o] = con ? (cf.next_of_x ? xn : dn) : T(0);
