@@ -35,6 +35,8 @@ __device__ __forceinline__ void aux_cell3(const Consts<double>& kc, const double
   }
 }
 
+}  // namespace
+
 // 3D: TX x TY tiles ordered x fastest, then y, then z-chunk (nzc chunks of zc node planes)
 template <int MODE, int TX, int TY>
 __global__ __launch_bounds__(64) void k_q1_aux3(CellParams cp, int zc, int ntx, int nzc, const double* __restrict__ U,
@@ -191,6 +193,8 @@ __global__ __launch_bounds__(64) void k_q1_aux2(CellParams cp, int zc, int ntx, 
     lon = hin;
   }
 }
+
+namespace {
 
 template <int MODE>
 pf_status launch_aux_mode(const Geom& g, const CellParams& cp, const double* U, const double* phit, double* y,

@@ -48,7 +48,8 @@ def sources_sha(paths):
 
 
 def short(name):
-    n = re.sub(r"\(.*", "", name).replace("void ", "").replace("pff::", "")
+    n = name.replace("(anonymous namespace)::", "")
+    n = re.sub(r"\(.*", "", n).replace("void ", "").replace("pff::", "")
     return n.strip()
 
 

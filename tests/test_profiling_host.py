@@ -122,3 +122,12 @@ def test_counters_means_and_sq_ratios(tmp_path):
     with pytest.raises(SystemExit):
         profiling.main(["counters", "--csv", str(tmp_path / "c.csv"), "--kernel", "k_missing",
                         "--out", str(out), "--command", "cmd"])
+
+
+def test_short_names_keep_namespaced_kernels():
+    # a kernel in an unnamed namespace demangles with a parenthesis before its own name
+    assert profiling.short("void pff::(anonymous namespace)::k_x<4, 8, 8>(pff::CellParams, int, double*)") == \
+        "k_x<4, 8, 8>"
+    assert profiling.short("void pff::k_q1_3d_slab<double, 0, false>(pff::CellParams, int)") == \
+        "k_q1_3d_slab<double, 0, false>"
+    assert profiling.short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
