@@ -207,6 +207,12 @@ pf_status multi_dot(const double* V, int64_t ld, int k, const double* w, int64_t
 // w -= sum_i h[i] V_i   (h on device)
 pf_status multi_axpy(double* w, const double* V, int64_t ld, int k, const double* d_h, int64_t n, double sign,
                      hipStream_t s);
+// One Gram-Schmidt pass fused with the reduction that follows it, for k <= kMultiDotRows:
+// w -= sum_i h[i] V_i, and in the same pass over w either d_out[i] = V_i . w (norm false) or
+// d_out[0] = |w|^2 (norm true), both of the updated w.  w and the dots take the values of
+// multi_axpy followed by multi_dot (the same reduction grid and order).
+pf_status axpy_then_dot(double* w, const double* V, int64_t ld, int k, const double* d_h, int64_t n, bool norm,
+                        double* d_partials, double* d_out, hipStream_t s);
 // y = x * (1/sqrt(*d_nrm2))
 pf_status vec_scale_inv_sqrt(double* y, const double* x, const double* d_nrm2, int64_t n, hipStream_t s);
 // sum of squares into d_out (device scalar)

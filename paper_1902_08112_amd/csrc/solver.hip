@@ -1063,10 +1063,16 @@ pf_status fgmres(pf_ctx* c, const double* b, double* x, int vprec, int* iters, d
       double* h2 = c->dscal + 256;
       double* nr = c->dscal + 512;
       PFF_TRY(multi_dot(c->V, n, j + 1, w, n, c->part_md, h1, s));
-      PFF_TRY(multi_axpy(w, c->V, n, j + 1, h1, n, -1.0, s));
-      PFF_TRY(multi_dot(c->V, n, j + 1, w, n, c->part_md, h2, s));
-      PFF_TRY(multi_axpy(w, c->V, n, j + 1, h2, n, -1.0, s));
-      PFF_TRY(nrm2_dev(w, n, c->part, nr, s));
+      if (j + 1 <= kMultiDotRows) {
+        // each subtraction shares its pass over w with the reduction after it
+        PFF_TRY(axpy_then_dot(w, c->V, n, j + 1, h1, n, false, c->part_md, h2, s));
+        PFF_TRY(axpy_then_dot(w, c->V, n, j + 1, h2, n, true, c->part_md, nr, s));
+      } else {
+        PFF_TRY(multi_axpy(w, c->V, n, j + 1, h1, n, -1.0, s));
+        PFF_TRY(multi_dot(c->V, n, j + 1, w, n, c->part_md, h2, s));
+        PFF_TRY(multi_axpy(w, c->V, n, j + 1, h2, n, -1.0, s));
+        PFF_TRY(nrm2_dev(w, n, c->part, nr, s));
+      }
       PFF_TRY(vec_scale_inv_sqrt(w, w, nr, n, s));
       // one copy of both Gram-Schmidt passes and the norm into pinned memory
       PFF_HIP(hipMemcpyAsync(hs, c->dscal, sizeof(double) * kHostScal, hipMemcpyDeviceToHost, s));

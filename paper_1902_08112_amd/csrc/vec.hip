@@ -302,6 +302,59 @@ pf_status multi_axpy(double* w, const double* V, int64_t ld, int k, const double
   return PF_OK;
 }
 
+// w -= sum_i h[i] V_i, then per-row partial dots of the new w with V_i (NORM false) or of w with
+// itself (NORM true); the grid and the per-thread order are those of k_multi_dot
+template <bool NORM>
+__global__ void k_axpy_dot(double* w, const double* V, int64_t ld, int k, const double* h, int64_t n,
+                           double* partials) {
+  double hh[kMultiDotRows], acc[kMultiDotRows];
+#pragma unroll
+  for (int i = 0; i < kMultiDotRows; ++i) {
+    hh[i] = i < k ? h[i] : 0.0;
+    acc[i] = 0.0;
+  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double v[kMultiDotRows];
+    double a = 0.0;
+#pragma unroll
+    for (int i = 0; i < kMultiDotRows; ++i) {
+      v[i] = i < k ? V[(int64_t)i * ld + t] : 0.0;
+      if (i < k) a += hh[i] * v[i];
+    }
+    const double wt = w[t] + -1.0 * a;
+    w[t] = wt;
+    if (NORM) {
+      acc[0] += wt * wt;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kMultiDotRows; ++i)
+        if (i < k) acc[i] += v[i] * wt;
+    }
+  }
+  const int rows = NORM ? 1 : k;
+  for (int i = 0; i < rows; ++i) {
+    const double b = block_sum(acc[i]);
+    if (threadIdx.x == 0) partials[(int64_t)i * gridDim.x + blockIdx.x] = b;
+  }
+}
+
+pf_status axpy_then_dot(double* w, const double* V, int64_t ld, int k, const double* d_h, int64_t n, bool norm,
+                        double* d_part, double* d_out, hipStream_t s) {
+  if (k < 1 || k > kMultiDotRows) {
+    set_error("axpy_then_dot: 1 to kMultiDotRows rows");
+    return PF_ERR_INVALID_ARG;
+  }
+  const int nb = (int)nblocks(n, kRedBlock * 8, kMultiDotBlocks);
+  if (norm)
+    k_axpy_dot<true><<<nb, kRedBlock, 0, s>>>(w, V, ld, k, d_h, n, d_part);
+  else
+    k_axpy_dot<false><<<nb, kRedBlock, 0, s>>>(w, V, ld, k, d_h, n, d_part);
+  PFF_CHECK_LAUNCH();
+  k_finalize_rows<<<norm ? 1 : k, kRedBlock, 0, s>>>(d_part, nb, d_out);
+  PFF_CHECK_LAUNCH();
+  return PF_OK;
+}
+
 __global__ void k_scale_inv_sqrt(double* y, const double* x, const double* nrm2, int64_t n) {
   const double nr = sqrt(*nrm2);
   const double f = nr > 0.0 ? 1.0 / nr : 0.0;
