@@ -351,6 +351,20 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
     const bool pre = kn <= z_hi && kn < cp.nn[2];
     uint8_t n0 = 0xFF, n1 = 0xFF;
     if (pre) fetch(kn, n0, n1);
+    // the fused step's operands at the lane's own node of plane kz, requested early so that the
+    // layer's cell math covers their latency: residual and diagonal here, the iterate before the
+    // phase-field rows
+    T fr[4] = {T(0), T(0), T(0), T(0)}, fd[4] = {T(1), T(1), T(1), T(1)};
+    if constexpr (CHEB) {
+      if (own_xy && kz >= z_lo) {
+        const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          fr[c] = cf.res[c * nn + go];
+          fd[c] = cf.diag[c * nn + go];
+        }
+      }
+    }
 
     const bool cell = cell_xy && kz >= 0 && kz < cp.N[2];
     const int lo = (kz + 3) % 3, hi = (kz + 4) % 3;
@@ -396,18 +410,12 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
     }
     // keep the compiler from carrying the corner values of the first part into the second
     __asm__ __volatile__("" ::: "memory");
-    // the fused step's operands at the lane's own node of plane kz (residual, diagonal, iterate),
-    // requested before the phase-field rows so that their math and the barrier cover the latency
-    T fr[4] = {T(0), T(0), T(0), T(0)}, fd[4] = {T(1), T(1), T(1), T(1)}, fx[4] = {T(0), T(0), T(0), T(0)};
+    T fx[4] = {T(0), T(0), T(0), T(0)};
     if constexpr (CHEB) {
       if (own_xy && kz >= z_lo) {
         const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          fr[c] = cf.res[c * nn + go];
-          fd[c] = cf.diag[c * nn + go];
-          fx[c] = cf.x[c * nn + go];
-        }
+        for (int c = 0; c < 4; ++c) fx[c] = cf.x[c * nn + go];
       }
     }
     // phase-field rows
