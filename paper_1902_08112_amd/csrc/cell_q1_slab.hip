@@ -246,6 +246,119 @@ __device__ __forceinline__ void phi_rows_layers(const Consts<T>& k, const T (*pl
   q1::grad3T(Gp, k.ih, out);
 }
 
+// All rows of G~ for one cell (FP64), the Gauss points one z-layer at a time: each layer's
+// gradient tables of du serve both the displacement rows (their stress tables accumulate over the
+// two layers before one backward contraction, as in cell3_u of q1_cell.h) and the coupled
+// phase-field rows (as in phi_rows_layers), so du is interpolated once per cell.
+template <typename T, int NF>
+__device__ __forceinline__ void g_rows_layers(const Consts<T>& k, const T (*plo)[kSPlanePad], const T (*phi_)[kSPlanePad],
+                                              int ln, const uint8_t mk[8], int u0, int ptf, const T dp[8],
+                                              T outu[3][8], T outp[8]) {
+  T P[3][3][4];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[c][j][r] = T(0);
+  T fv[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __asm__ __volatile__("" ::: "memory");
+    T gd0[3][2], gd1[3][2], gd2[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T f[8];
+      corners<T>(&plo[c][0], &phi_[c][0], ln, f);
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+        if (mk[a] & (1 << c)) f[a] = T(0);
+      grad3_layer<T>(f, k.ih, h, gd0[c], gd1[c], gd2[c]);
+    }
+    T pq[4];
+    {
+      T f[8];
+      corners<T>(&plo[ptf][0], &phi_[ptf][0], ln, f);
+      val3_layer<T>(f, h, pq);
+    }
+    // displacement rows: g(phi~) sigma(du) at the layer's points into the stress tables
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int qx = qq & 1, qy = qq >> 1;
+      const int r0 = qy + 2 * h, r1 = qx + 2 * h, r2 = qq;
+      const T g00 = gd0[0][qy], g01 = gd1[0][qx], g02 = gd2[0][qq];
+      const T g10 = gd0[1][qy], g11 = gd1[1][qx], g12 = gd2[1][qq];
+      const T g20 = gd0[2][qy], g21 = gd1[2][qx], g22 = gd2[2][qq];
+      const T gw = ((T(1) - k.kap) * pq[qq] * pq[qq] + k.kap) * k.jxw;
+      const T lt = k.lam * (g00 + g11 + g22);
+      const T tm = T(2) * k.mu;
+      const T s00 = gw * (tm * g00 + lt), s11 = gw * (tm * g11 + lt), s22 = gw * (tm * g22 + lt);
+      const T s01 = gw * k.mu * (g01 + g10), s02 = gw * k.mu * (g02 + g20), s12 = gw * k.mu * (g12 + g21);
+      P[0][0][r0] += s00;
+      P[0][1][r1] += s01;
+      P[0][2][r2] += s02;
+      P[1][0][r0] += s01;
+      P[1][1][r1] += s11;
+      P[1][2][r2] += s12;
+      P[2][0][r0] += s02;
+      P[2][1][r1] += s12;
+      P[2][2][r2] += s22;
+    }
+    __asm__ __volatile__("" ::: "memory");
+    T gu0[3][2], gu1[3][2], gu2[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      T f[8];
+      corners<T>(&plo[u0 + c][0], &phi_[u0 + c][0], ln, f);
+      grad3_layer<T>(f, k.ih, h, gu0[c], gu1[c], gu2[c]);
+    }
+    T pv[4], dv[4];
+    {
+      T f[8];
+      corners<T>(&plo[u0 + 3][0], &phi_[u0 + 3][0], ln, f);
+      val3_layer<T>(f, h, pv);
+    }
+    val3_layer<T>(dp, h, dv);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int qx = qq & 1, qy = qq >> 1;
+      const T e00 = gu0[0][qy], e11 = gu1[1][qx], e22 = gu2[2][qq];
+      const T e01 = T(0.5) * (gu1[0][qx] + gu0[1][qy]);
+      const T e02 = T(0.5) * (gu2[0][qq] + gu0[2][qy]);
+      const T e12 = T(0.5) * (gu2[1][qq] + gu1[2][qx]);
+      const T tru = e00 + e11 + e22;
+      const T ee = e00 * e00 + e11 * e11 + e22 * e22 + T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
+      const T Es = T(0.5) * k.lam * tru * tru + k.mu * ee;
+      const T cphi = (T(1) - k.kap) * Es + T(2) * k.pres * tru + k.gce;
+      const T d00 = gd0[0][qy], d11 = gd1[1][qx], d22 = gd2[2][qq];
+      const T d01 = T(0.5) * (gd1[0][qx] + gd0[1][qy]);
+      const T d02 = T(0.5) * (gd2[0][qq] + gd0[2][qy]);
+      const T d12 = T(0.5) * (gd2[1][qq] + gd1[2][qx]);
+      const T trd = d00 + d11 + d22;
+      const T eed = e00 * d00 + e11 * d11 + e22 * d22 + T(2) * (e01 * d01 + e02 * d02 + e12 * d12);
+      const T sde = T(2) * k.mu * eed + k.lam * tru * trd;
+      fv[qq + 4 * h] = (cphi * dv[qq] + pv[qq] * ((T(1) - k.kap) * sde + T(2) * k.pres * trd)) * k.jxw;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
+    q1::grad3T(P[c], k.ih, outu[c]);
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) outp[a] = T(0);
+  q1::val3T(fv, outp);
+  T Gp[3][4];
+  q1::grad3(dp, k.ih, Gp);
+  const T s = T(2) * k.gcx * k.jxw;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gp[j][r] *= s;
+  q1::grad3T(Gp, k.ih, outp);
+}
+
 }  // namespace
 
 // Occupancy: the FP64 Jacobian and the FP64 fused step keep 256 registers at 2 waves per SIMD
@@ -378,89 +491,118 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
       }
     }
     T Y[4][2];
-    // displacement rows
-    {
-      T outu[3][8];
-      if (cell) {
-        T du[3][8], pt[8];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
-#pragma unroll
-          for (int a = 0; a < 8; ++a)
-            if (mk[a] & (1 << c)) du[c][a] = T(0);
-        }
-        corners<T>(&sv[lo][F::PT][0], &sv[hi][F::PT][0], ln, pt);
-        cell3_u<T>(kc, du, pt, outu);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        T X1[2];
-        combine_xy<T>(outu[c], first_row, Y[c], X1);
-        if (last_row && wave < kSWaves - 1) {
-          sx[par][wave][i][2 * c] = X1[0];
-          sx[par][wave][i][2 * c + 1] = X1[1];
-        }
-      }
-    }
-    // keep the compiler from carrying the corner values of the first part into the second
-    __asm__ __volatile__("" ::: "memory");
-    T fx[4] = {T(0), T(0), T(0), T(0)};
-    if constexpr (CHEB) {
-      if (own_xy && kz >= z_lo) {
-        const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fx[c] = cf.x[c * nn + go];
-      }
-    }
-    // phase-field rows
-    {
-      T outp[8];
+    T fx[4] = {T(0), T(0), T(0), T(0)};  // the fused step's iterate at the own node (requested below)
+    if constexpr (MODE == MODE_APPLY && sizeof(T) == 8) {
+      // FP64 G~: displacement and phase-field rows from the same per-layer tables of du
+      T outu[3][8], outp[8];
       if (cell) {
         T dp[8];
         corners<T>(&sv[lo][3][0], &sv[hi][3][0], ln, dp);
 #pragma unroll
         for (int a = 0; a < 8; ++a)
           if (mk[a] & kMaskPhi) dp[a] = T(0);
-        if constexpr (MODE == MODE_BLOCK) {
-          const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)kz * cp.N[0] * cp.N[1];
-          T cq[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) cq[q] = qcb[q * cp.n_cells + cid];
-          cell3_phi_stored<T>(kc, dp, cq, outp);
-        } else {
-          if constexpr (sizeof(T) == 8) {
-            // FP64: one Gauss layer at a time (the whole-cell tables would spill at 2 waves/SIMD)
-            phi_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, dp, outp);
-          } else {
-            // FP32 fits the whole-cell tables (fewer operations than the layered form)
-            T du[3][8], uu[3][8], ph[8];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
-#pragma unroll
-              for (int a = 0; a < 8; ++a)
-                if (mk[a] & (1 << c)) du[c][a] = T(0);
-              corners<T>(&sv[lo][F::U0 + c][0], &sv[hi][F::U0 + c][0], ln, uu[c]);
-            }
-            corners<T>(&sv[lo][F::U0 + 3][0], &sv[hi][F::U0 + 3][0], ln, ph);
-            cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
-          }
-        }
+        g_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, F::PT, dp, outu, outp);
       } else {
 #pragma unroll
-        for (int a = 0; a < 8; ++a) outp[a] = T(0);
+        for (int a = 0; a < 8; ++a) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) outu[c][a] = T(0);
+          outp[a] = T(0);
+        }
       }
-      T X1[2];
-      combine_xy<T>(outp, first_row, Y[3], X1);
-      if (last_row && wave < kSWaves - 1) {
-        sx[par][wave][i][6] = X1[0];
-        sx[par][wave][i][7] = X1[1];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T X1[2];
+        combine_xy<T>(c < 3 ? outu[c] : outp, first_row, Y[c], X1);
+        if (last_row && wave < kSWaves - 1) {
+          sx[par][wave][i][2 * c] = X1[0];
+          sx[par][wave][i][2 * c + 1] = X1[1];
+        }
+      }
+    } else {
+      // displacement rows
+      {
+        T outu[3][8];
+        if (cell) {
+          T du[3][8], pt[8];
+  #pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
+  #pragma unroll
+            for (int a = 0; a < 8; ++a)
+              if (mk[a] & (1 << c)) du[c][a] = T(0);
+          }
+          corners<T>(&sv[lo][F::PT][0], &sv[hi][F::PT][0], ln, pt);
+          cell3_u<T>(kc, du, pt, outu);
+        } else {
+  #pragma unroll
+          for (int c = 0; c < 3; ++c)
+  #pragma unroll
+            for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
+        }
+  #pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T X1[2];
+          combine_xy<T>(outu[c], first_row, Y[c], X1);
+          if (last_row && wave < kSWaves - 1) {
+            sx[par][wave][i][2 * c] = X1[0];
+            sx[par][wave][i][2 * c + 1] = X1[1];
+          }
+        }
+      }
+      // keep the compiler from carrying the corner values of the first part into the second
+      __asm__ __volatile__("" ::: "memory");
+      if constexpr (CHEB) {
+        if (own_xy && kz >= z_lo) {
+          const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
+  #pragma unroll
+          for (int c = 0; c < 4; ++c) fx[c] = cf.x[c * nn + go];
+        }
+      }
+      // phase-field rows
+      {
+        T outp[8];
+        if (cell) {
+          T dp[8];
+          corners<T>(&sv[lo][3][0], &sv[hi][3][0], ln, dp);
+  #pragma unroll
+          for (int a = 0; a < 8; ++a)
+            if (mk[a] & kMaskPhi) dp[a] = T(0);
+          if constexpr (MODE == MODE_BLOCK) {
+            const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)kz * cp.N[0] * cp.N[1];
+            T cq[8];
+  #pragma unroll
+            for (int q = 0; q < 8; ++q) cq[q] = qcb[q * cp.n_cells + cid];
+            cell3_phi_stored<T>(kc, dp, cq, outp);
+          } else {
+            if constexpr (sizeof(T) == 8) {
+              // FP64: one Gauss layer at a time (the whole-cell tables would spill at 2 waves/SIMD)
+              phi_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, dp, outp);
+            } else {
+              // FP32 fits the whole-cell tables (fewer operations than the layered form)
+              T du[3][8], uu[3][8], ph[8];
+  #pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
+  #pragma unroll
+                for (int a = 0; a < 8; ++a)
+                  if (mk[a] & (1 << c)) du[c][a] = T(0);
+                corners<T>(&sv[lo][F::U0 + c][0], &sv[hi][F::U0 + c][0], ln, uu[c]);
+              }
+              corners<T>(&sv[lo][F::U0 + 3][0], &sv[hi][F::U0 + 3][0], ln, ph);
+              cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+            }
+          }
+        } else {
+  #pragma unroll
+          for (int a = 0; a < 8; ++a) outp[a] = T(0);
+        }
+        T X1[2];
+        combine_xy<T>(outp, first_row, Y[3], X1);
+        if (last_row && wave < kSWaves - 1) {
+          sx[par][wave][i][6] = X1[0];
+          sx[par][wave][i][7] = X1[1];
+        }
       }
     }
     // the own node's input values and mask on plane kz, read before the barrier: after it the
