@@ -172,84 +172,15 @@ __device__ __forceinline__ void val3_layer(const T f[8], int h, T v[4]) {
   v[3] = a1 + x1 * (b1 - a1);
 }
 
-// Phase-field rows of G~ (the coupled rows of cell3_phi in q1_cell.h) with the Gauss points taken
-// one z-layer at a time, the corners of u, du and phi re-read from LDS for each layer, so that the
-// gradient tables of u and of du are never both whole in registers (FP64: the whole-cell form
-// spills at two waves per SIMD and is 24% slower on 256^3; FP32 keeps the whole-cell form, which
-// needs fewer operations and does not spill).
-//   f(q) = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) dphi + phi ((1-kappa) sigma(u):e(du) + 2 p div du)
+// All rows of G~ for one cell (FP64), the Gauss points one z-layer at a time, the corners of u, du
+// and phi re-read from LDS for each layer, so that the gradient tables of u and of du are never
+// both whole in registers (the whole-cell form spills at two waves per SIMD).  Each layer's tables
+// of du serve both the displacement rows (their stress tables accumulate over the two layers
+// before one backward contraction, as in cell3_u of q1_cell.h) and the coupled phase-field rows
+// (cell3_phi), so du is interpolated once per cell.
+//   phase-field rows: f(q) = ((1-kappa) E_s(u) + 2 p div u + G_c/eps) dphi
+//                            + phi ((1-kappa) sigma(u):e(du) + 2 p div du),
 //   out[a] = sum_q f(q) JxW N_a(q) + G_c eps grad dphi . grad N_a JxW
-template <typename T, int NF>
-__device__ __forceinline__ void phi_rows_layers(const Consts<T>& k, const T (*plo)[kSPlanePad], const T (*phi_)[kSPlanePad],
-                                                int ln, const uint8_t mk[8], int u0, const T dp[8], T out[8]) {
-  T fv[8];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    // no LDS read of this layer moves above the previous layer's arithmetic
-    __asm__ __volatile__("" ::: "memory");
-    T gu0[3][2], gu1[3][2], gu2[3][4];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T f[8];
-      corners<T>(&plo[u0 + c][0], &phi_[u0 + c][0], ln, f);
-      grad3_layer<T>(f, k.ih, h, gu0[c], gu1[c], gu2[c]);
-    }
-    __asm__ __volatile__("" ::: "memory");
-    T gd0[3][2], gd1[3][2], gd2[3][4];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      T f[8];
-      corners<T>(&plo[c][0], &phi_[c][0], ln, f);
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (mk[a] & (1 << c)) f[a] = T(0);
-      grad3_layer<T>(f, k.ih, h, gd0[c], gd1[c], gd2[c]);
-    }
-    T pv[4], dv[4];
-    {
-      T f[8];
-      corners<T>(&plo[u0 + 3][0], &phi_[u0 + 3][0], ln, f);
-      val3_layer<T>(f, h, pv);
-    }
-    val3_layer<T>(dp, h, dv);
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int qx = qq & 1, qy = qq >> 1;
-      const T e00 = gu0[0][qy], e11 = gu1[1][qx], e22 = gu2[2][qq];
-      const T e01 = T(0.5) * (gu1[0][qx] + gu0[1][qy]);
-      const T e02 = T(0.5) * (gu2[0][qq] + gu0[2][qy]);
-      const T e12 = T(0.5) * (gu2[1][qq] + gu1[2][qx]);
-      const T tru = e00 + e11 + e22;
-      const T ee = e00 * e00 + e11 * e11 + e22 * e22 + T(2) * (e01 * e01 + e02 * e02 + e12 * e12);
-      const T Es = T(0.5) * k.lam * tru * tru + k.mu * ee;
-      const T cphi = (T(1) - k.kap) * Es + T(2) * k.pres * tru + k.gce;
-      const T d00 = gd0[0][qy], d11 = gd1[1][qx], d22 = gd2[2][qq];
-      const T d01 = T(0.5) * (gd1[0][qx] + gd0[1][qy]);
-      const T d02 = T(0.5) * (gd2[0][qq] + gd0[2][qy]);
-      const T d12 = T(0.5) * (gd2[1][qq] + gd1[2][qx]);
-      const T trd = d00 + d11 + d22;
-      const T eed = e00 * d00 + e11 * d11 + e22 * d22 + T(2) * (e01 * d01 + e02 * d02 + e12 * d12);
-      const T sde = T(2) * k.mu * eed + k.lam * tru * trd;
-      fv[qq + 4 * h] = (cphi * dv[qq] + pv[qq] * ((T(1) - k.kap) * sde + T(2) * k.pres * trd)) * k.jxw;
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 8; ++a) out[a] = T(0);
-  q1::val3T(fv, out);
-  T Gp[3][4];
-  q1::grad3(dp, k.ih, Gp);
-  const T s = T(2) * k.gcx * k.jxw;
-#pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Gp[j][r] *= s;
-  q1::grad3T(Gp, k.ih, out);
-}
-
-// All rows of G~ for one cell (FP64), the Gauss points one z-layer at a time: each layer's
-// gradient tables of du serve both the displacement rows (their stress tables accumulate over the
-// two layers before one backward contraction, as in cell3_u of q1_cell.h) and the coupled
-// phase-field rows (as in phi_rows_layers), so du is interpolated once per cell.
 template <typename T, int NF>
 __device__ __forceinline__ void g_rows_layers(const Consts<T>& k, const T (*plo)[kSPlanePad], const T (*phi_)[kSPlanePad],
                                               int ln, const uint8_t mk[8], int u0, int ptf, const T dp[8],
@@ -525,22 +456,22 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
         T outu[3][8];
         if (cell) {
           T du[3][8], pt[8];
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 3; ++c) {
             corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
-  #pragma unroll
+#pragma unroll
             for (int a = 0; a < 8; ++a)
               if (mk[a] & (1 << c)) du[c][a] = T(0);
           }
           corners<T>(&sv[lo][F::PT][0], &sv[hi][F::PT][0], ln, pt);
           cell3_u<T>(kc, du, pt, outu);
         } else {
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 3; ++c)
-  #pragma unroll
+#pragma unroll
             for (int a = 0; a < 8; ++a) outu[c][a] = T(0);
         }
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
           T X1[2];
           combine_xy<T>(outu[c], first_row, Y[c], X1);
@@ -555,7 +486,7 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
       if constexpr (CHEB) {
         if (own_xy && kz >= z_lo) {
           const int64_t go = (int64_t)cx + (int64_t)cy * sy + (int64_t)kz * sz;
-  #pragma unroll
+#pragma unroll
           for (int c = 0; c < 4; ++c) fx[c] = cf.x[c * nn + go];
         }
       }
@@ -565,36 +496,31 @@ __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 && (MODE == MODE_APPLY || CHE
         if (cell) {
           T dp[8];
           corners<T>(&sv[lo][3][0], &sv[hi][3][0], ln, dp);
-  #pragma unroll
+#pragma unroll
           for (int a = 0; a < 8; ++a)
             if (mk[a] & kMaskPhi) dp[a] = T(0);
           if constexpr (MODE == MODE_BLOCK) {
             const int64_t cid = (int64_t)cx + (int64_t)cy * cp.N[0] + (int64_t)kz * cp.N[0] * cp.N[1];
             T cq[8];
-  #pragma unroll
+#pragma unroll
             for (int q = 0; q < 8; ++q) cq[q] = qcb[q * cp.n_cells + cid];
             cell3_phi_stored<T>(kc, dp, cq, outp);
           } else {
-            if constexpr (sizeof(T) == 8) {
-              // FP64: one Gauss layer at a time (the whole-cell tables would spill at 2 waves/SIMD)
-              phi_rows_layers<T, F::NF>(kc, sv[lo], sv[hi], ln, mk, F::U0, dp, outp);
-            } else {
-              // FP32 fits the whole-cell tables (fewer operations than the layered form)
-              T du[3][8], uu[3][8], ph[8];
-  #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
-  #pragma unroll
-                for (int a = 0; a < 8; ++a)
-                  if (mk[a] & (1 << c)) du[c][a] = T(0);
-                corners<T>(&sv[lo][F::U0 + c][0], &sv[hi][F::U0 + c][0], ln, uu[c]);
-              }
-              corners<T>(&sv[lo][F::U0 + 3][0], &sv[hi][F::U0 + 3][0], ln, ph);
-              cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
+            // FP32 G~ (FP64 takes g_rows_layers above): the whole-cell tables fit its registers
+            T du[3][8], uu[3][8], ph[8];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              corners<T>(&sv[lo][c][0], &sv[hi][c][0], ln, du[c]);
+#pragma unroll
+              for (int a = 0; a < 8; ++a)
+                if (mk[a] & (1 << c)) du[c][a] = T(0);
+              corners<T>(&sv[lo][F::U0 + c][0], &sv[hi][F::U0 + c][0], ln, uu[c]);
             }
+            corners<T>(&sv[lo][F::U0 + 3][0], &sv[hi][F::U0 + 3][0], ln, ph);
+            cell3_phi<T, COUPLE>(kc, du, dp, uu, ph, outp);
           }
         } else {
-  #pragma unroll
+#pragma unroll
           for (int a = 0; a < 8; ++a) outp[a] = T(0);
         }
         T X1[2];
